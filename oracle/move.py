@@ -1,0 +1,120 @@
+"""Data movement of the exchange, and the plain definitions it must reproduce.
+
+TEST INFRASTRUCTURE (see the package docstring).
+
+Source passages (MPI Advance, 2023): Listings 3 and 4 (all-to-all-v buffers
+described by counts and displacements; Start / Wait of the persistent
+request), Sec. 2.2 (locality-aware aggregation with forwarding inside a node)
+and Sec. 2.4 (the same calls accept device memory, so the pack of a send
+buffer from a vector and the unpack into the halo are device-side gathers).
+
+The message transfer between ranks is simulated here by copying each
+message's segment from the sender's buffer into the receiver's buffer.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def pack(x_local: np.ndarray, idx) -> np.ndarray:
+    """Pack (Start): send[k, :] = x_local[idx[k], :]."""
+    return np.take(x_local, np.asarray(idx, np.int64), axis=0)
+
+
+def gather_rows(src: np.ndarray, idx) -> np.ndarray:
+    """Redistribution pack and unpack: out[k, :] = src[idx[k], :]."""
+    return np.take(src, np.asarray(idx, np.int64), axis=0)
+
+
+def transfer(send_bufs: list, send_lists: list, recv_lists: list) -> list:
+    """Simulated message transfer for every rank at once.
+
+    ``send_lists[q]`` / ``recv_lists[r]`` are (procs, counts, displs).  The
+    message r receives from q is the segment of q's send buffer addressed to r.
+    """
+    R = len(send_bufs)
+    out = []
+    for r in range(R):
+        rp, rc, rd = recv_lists[r]
+        tail = send_bufs[0].shape[1:] if R else ()
+        dt = send_bufs[0].dtype if R else np.float64
+        buf = np.empty((int(np.sum(rc, dtype=np.int64)),) + tail, dt)
+        for q, c, d in zip(rp, rc, rd):
+            sp, sc, sd = send_lists[q]
+            pos = np.nonzero(np.asarray(sp) == r)[0]
+            if pos.size != 1 or int(sc[pos[0]]) != int(c):
+                raise AssertionError(f"message {q}->{r} not matched")
+            s0 = int(sd[pos[0]])
+            buf[int(d):int(d) + int(c)] = send_bufs[q][s0:s0 + int(c)]
+        out.append(buf)
+    return out
+
+
+def forward_all(plans: list, x_global: np.ndarray, row_starts) -> dict:
+    """Run Start and Wait for every rank with simulated transfers.
+
+    Start: pack the stage-1 send buffer.  Wait: receive stage 1, pack the
+    stage-2 (redistribution) buffer from the stage-1 receive buffer, receive
+    stage 2, unpack [stage-1 recv | stage-2 recv] into the halo.
+    Returns every intermediate buffer (per rank lists).
+    """
+    R = len(plans)
+    rs = np.asarray(row_starts, np.int64)
+    send1 = [pack(x_global[rs[p]:rs[p + 1]], plans[p]["s1_idx"]) for p in range(R)]
+    recv1 = transfer(send1, [(p["s1_procs"], p["s1_counts"], p["s1_displs"]) for p in plans],
+                     [(p["r1_procs"], p["r1_counts"], p["r1_displs"]) for p in plans])
+    send2 = [gather_rows(recv1[p], plans[p]["s2_src"]) for p in range(R)]
+    recv2 = transfer(send2, [(p["s2_procs"], p["s2_counts"], p["s2_displs"]) for p in plans],
+                     [(p["r2_procs"], p["r2_counts"], p["r2_displs"]) for p in plans])
+    arena = [np.concatenate([recv1[p], recv2[p]], axis=0) for p in range(R)]
+    halo = [gather_rows(arena[p], plans[p]["unpack_src"]) for p in range(R)]
+    return dict(send1=send1, recv1=recv1, send2=send2, recv2=recv2, arena=arena, halo=halo)
+
+
+def halo_reference(x_global: np.ndarray, halo_cols) -> np.ndarray:
+    """Plain definition of the exchange result: the direct global gather x[N_r]."""
+    return np.take(x_global, np.asarray(halo_cols, np.int64), axis=0)
+
+
+def segmented_sum_fixed_order(vals: np.ndarray, seg_ptr, order) -> np.ndarray:
+    """out[i] = vals[order[seg_ptr[i]]] + vals[order[seg_ptr[i]+1]] + ... in that order.
+
+    Sequential additions in the dtype of ``vals`` (no pairwise or tree
+    reduction), the accumulator starting from the first term (so a lone -0.0
+    stays -0.0); an empty segment yields +0.0.  Vectorised over segments by
+    depth: step d adds the d-th term of every segment longer than d.
+    """
+    seg_ptr = np.asarray(seg_ptr, np.int64)
+    order = np.asarray(order, np.int64)
+    nseg = seg_ptr.size - 1
+    out = np.zeros((nseg,) + vals.shape[1:], vals.dtype)
+    lens = np.diff(seg_ptr)
+    if nseg == 0 or lens.size == 0 or lens.max(initial=0) == 0:
+        return out
+    rows = np.nonzero(lens > 0)[0]
+    out[rows] = vals[order[seg_ptr[rows]]]
+    for d in range(1, int(lens.max())):
+        rows = np.nonzero(lens > d)[0]
+        out[rows] = out[rows] + vals[order[seg_ptr[rows] + d]]
+    return out
+
+
+def pack_transpose(g_send: np.ndarray, bt_ptr, bt_perm) -> np.ndarray:
+    """Backward of the pack: gX[i] = sum of g_send[k] over k with idx[k] == i,
+    in ascending k (the transpose CSR of the pack map)."""
+    return segmented_sum_fixed_order(g_send, bt_ptr, bt_perm)
+
+
+def exchange_adjoint_reference(halos: list, g_halos: list, n: int) -> np.ndarray:
+    """Plain definition of the backward of the whole exchange (closed form G^T).
+
+    gX[c] = sum over ranks s (ascending) whose halo holds column c of the
+    gradient of that halo entry.  Rows referenced by no halo get +0.0.
+    """
+    cols = np.concatenate([np.asarray(h, np.int64) for h in halos]) if halos else np.zeros(0, np.int64)
+    vals = np.concatenate(g_halos, axis=0)
+    order = np.argsort(cols, kind="stable")   # concatenation is in ascending s
+    counts = np.bincount(cols, minlength=n)
+    ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(counts, out=ptr[1:])
+    return segmented_sum_fixed_order(vals, ptr, order)
