@@ -1,0 +1,280 @@
+/*
+ * hx.h -- C ABI of the MI355X (gfx950) halo-exchange buffer engine.
+ *
+ * The library implements the rank-local buffer work underneath a persistent
+ * neighborhood all-to-all-v used for a sparse-matrix halo exchange, as
+ * described for MPI Advance (Bienz, Schafer, Skjellum, 2023):
+ *
+ *   - Sec. 2.2 and Listing 4: a neighbor topology, a persistent request
+ *     created once (all setup cost paid at initialisation), then driven by
+ *     Start / Wait every iteration;
+ *   - Sec. 2.2, last paragraph: a locality-aware variant, given unique global
+ *     indices of every value exchanged, that sends a value between a pair of
+ *     nodes only once and redistributes it inside the node;
+ *   - Sec. 2.4: the calls accept device memory, so packing a send buffer from
+ *     a vector and unpacking received data into the halo are device gathers.
+ *
+ * Start packs (indexed row gather from the local vector); Wait runs the
+ * on-node redistribution pack (locality variant) and unpacks into the halo.
+ * The message transfer itself is not part of this library: a request exposes
+ * its send and receive arenas, and a whole-decomposition batch ("world")
+ * can simulate the transfer by copying between its ranks' arenas in the same
+ * device memory.
+ *
+ * Conventions shared by all entry points
+ *   - Every call returns an int: HX_SUCCESS (0) or a negative HX_ERR_* code.
+ *     On HX_ERR_HIP, hx_last_hip_error() gives the hipError_t value.
+ *     Errors are reported per calling thread (hx_last_error_message()).
+ *   - Handles are opaque and returned through out-pointers; *_free(&h) sets
+ *     h to NULL and accepts NULL.
+ *   - "host" arrays are read during the call only and may be freed after it.
+ *     "device" pointers must stay valid, unmoved and unreallocated from the
+ *     call that binds them until the handle is freed (persistent semantics).
+ *   - Streams are hipStream_t passed as void*; NULL means the legacy default
+ *     stream.  Work is stream-ordered: a call returns once its kernels are
+ *     enqueued; results are complete when the stream reaches that point.
+ *   - Vectors are row-major [rows, ncols] of HX_F32 or HX_F64; one "row" is
+ *     the unit every list indexes.  All index arrays are int32; every
+ *     arena, halo, vector and plan must stay below 2^31 rows.
+ *   - Global ownership is contiguous: rank p owns the rows/columns
+ *     [row_starts[p], row_starts[p+1]).  Nodes are blocks of ppn consecutive
+ *     ranks (the last node may be partial).
+ */
+#ifndef HX_H
+#define HX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HX_SUCCESS = 0,
+  HX_ERR_ARG = -1,         /* null handle/pointer, negative size, counts/displs inconsistent */
+  HX_ERR_RANGE = -2,       /* an index outside its valid range */
+  HX_ERR_STATE = -3,       /* persistent request used in the wrong state */
+  HX_ERR_NOMEM = -4,       /* a device or host allocation failed */
+  HX_ERR_UNSUPPORTED = -5, /* reorder != 0, sizes beyond int32 rows, unsupported variant */
+  HX_ERR_HIP = -6          /* a HIP runtime call failed */
+};
+
+typedef enum { HX_F32 = 0, HX_F64 = 1 } hx_dtype;
+typedef enum { HX_PLAIN = 0, HX_LOCALITY_2STEP = 1 } hx_variant;
+
+typedef struct hx_topo hx_topo;
+typedef struct hx_plan hx_plan;
+typedef struct hx_req hx_req;
+typedef struct hx_batch hx_batch;
+
+/* Launch schedule of the gather / segmented-sum kernels.  A zero field means
+ * "library default".  per_neighbor = 1 splits each message into its own job
+ * (tiles never straddle neighbors); 0 tiles each member's rows flat. */
+typedef struct {
+  int tile_rows;      /* rows per tile (work unit of one workgroup iteration) */
+  int block_threads;  /* 256 or 512 */
+  int blocks_per_cu;  /* persistent grid = blocks_per_cu * #CUs */
+  int nontemporal;    /* 1: streaming (non-temporal) loads/stores of index and output */
+  int per_neighbor;   /* see above */
+} hx_sched;
+
+/* ---------------------------------------------------------------------------
+ * Errors
+ * ------------------------------------------------------------------------- */
+const char* hx_error_string(int code);
+int hx_last_hip_error(void);
+const char* hx_last_error_message(void);
+/* Library version string (build identifier). */
+const char* hx_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Neighbor topology -- Listing 4 (MPIX_Dist_graph_create_adjacent).
+ *
+ * rank, nranks: this rank and the size of the (simulated) communicator.
+ * recv_procs[n_recvs], send_procs[n_sends] (host): distinct neighbor ranks in
+ * [0, nranks), none equal to rank.  Weights are accepted and ignored (may be
+ * NULL).  reorder must be 0 (HX_ERR_UNSUPPORTED otherwise), since ranks are
+ * fixed by the decomposition.  HX_ERR_RANGE on an out-of-range or duplicate
+ * neighbor.  The handle owns host copies of the lists.
+ * ------------------------------------------------------------------------- */
+int hx_topo_create(int rank, int nranks, int n_recvs, const int* recv_procs,
+                   const int* recv_weights, int n_sends, const int* send_procs,
+                   const int* send_weights, int reorder, hx_topo** out);
+int hx_topo_free(hx_topo** topo);
+
+/* ---------------------------------------------------------------------------
+ * Persistent plain request -- Listing 4 (MPIX_Neighbor_alltoallv_init).
+ *
+ * x_local   device [n_local, ncols]: the vector the send buffer is packed from.
+ * sendcounts, sdispls (host [n_sends]): all-to-all-v layout of the send arena;
+ *           sdispls may be NULL, otherwise it must equal the exclusive prefix
+ *           sum of sendcounts (the arena is packed densely, neighbor order).
+ * send_idx  host [sum(sendcounts)]: the local row of x_local copied into each
+ *           send slot (the pack map), each in [0, n_local).
+ * halo      device [sum(recvcounts), ncols]: receives the unpacked values in
+ *           neighbor order (the plain unpack is the identity copy of the
+ *           receive arena into the halo).
+ * recvcounts, rdispls (host [n_recvs]): as for the send side.
+ * The library allocates and owns the send and receive arenas
+ * (hx_req_arena) and the device copies of all lists, and builds the
+ * transpose of the pack map (rows -> send slots, ascending) for hx_backward.
+ * Errors: HX_ERR_ARG (nulls, counts < 0, displs not the prefix sum),
+ * HX_ERR_RANGE (send_idx out of range), HX_ERR_UNSUPPORTED (>= 2^31 rows).
+ * ------------------------------------------------------------------------- */
+int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local,
+                               const int* sendcounts, const int* sdispls, const int* send_idx,
+                               void* halo, const int* recvcounts, const int* rdispls,
+                               hx_dtype dtype, int ncols, const hx_topo* topo, hx_req** out);
+
+/* ---------------------------------------------------------------------------
+ * Plans of a whole decomposition, built on the GPU (all setup at init,
+ * Sec. 2.2), for the plain variant or the 2-step locality-aware variant.
+ *
+ * hx_plan_from_csr: halo discovery from the sparse structure, then as below.
+ *   row_starts host [nranks+1] int64, increasing, row_starts[0] = 0, n = row_starts[nranks];
+ *   row_ptr    device [n+1] int64 (CSR row pointers);
+ *   cols       device [row_ptr[n]] int32, each in [0, n).
+ * hx_plan_from_halos: the locality-aware extension's input (Sec. 2.2, last
+ *   paragraph): the unique global indices every rank receives.
+ *   halo_ptr   host [nranks+1] int64; halo_cols device [halo_ptr[nranks]] int32,
+ *   strictly increasing within each rank and never owned by that rank.
+ * For each rank the plan holds (the lists a persistent init would build):
+ *   halo, stage-1 send/recv lists (plain: all messages; locality: on-node
+ *   messages plus one deduplicated message per remote node, sent to the
+ *   rank with the same local rank there), stage-2 (redistribution) lists,
+ *   the unpack map into the halo, and the transpose of the pack map.
+ * ppn >= 1 ranks per node (ignored by HX_PLAIN).  The plan owns its device
+ * arrays; inputs are read during the call only.  The call synchronises
+ * stream before returning.  Errors: HX_ERR_ARG, HX_ERR_RANGE (column out of
+ * range, halo not strictly increasing or owned by its rank),
+ * HX_ERR_UNSUPPORTED (sizes beyond int32 or the dense rank-pair tables
+ * exceeding HX_PLAN_MAX_RANKS ranks).
+ * ------------------------------------------------------------------------- */
+#define HX_PLAN_MAX_RANKS 16384
+int hx_plan_from_csr(int nranks, const int64_t* row_starts, int ppn, hx_variant variant,
+                     const int64_t* row_ptr, const int32_t* cols, void* stream, hx_plan** out);
+int hx_plan_from_halos(int nranks, const int64_t* row_starts, int ppn, hx_variant variant,
+                       const int64_t* halo_ptr, const int32_t* halo_cols, void* stream,
+                       hx_plan** out);
+int hx_plan_free(hx_plan** plan);
+
+/* Per-rank plan arrays, copied to host memory.  Field ids and element counts
+ * (all int32): */
+typedef enum {
+  HX_F_HALO = 0,      /* [H]        global column ids of the halo, ascending */
+  HX_F_S1_PROCS,      /* [n_s1]     stage-1 destinations, ascending */
+  HX_F_S1_COUNTS,     /* [n_s1] */
+  HX_F_S1_DISPLS,     /* [n_s1]     exclusive prefix of counts */
+  HX_F_S1_IDX,        /* [E1]       local row packed into each stage-1 send slot */
+  HX_F_R1_PROCS,      /* [n_r1]     stage-1 sources, ascending */
+  HX_F_R1_COUNTS,     /* [n_r1] */
+  HX_F_R1_DISPLS,     /* [n_r1] */
+  HX_F_S2_PROCS,      /* [n_s2]     redistribution destinations (same node) */
+  HX_F_S2_COUNTS,     /* [n_s2] */
+  HX_F_S2_DISPLS,     /* [n_s2] */
+  HX_F_S2_SRC,        /* [E2]       stage-1 receive slot forwarded by each stage-2 send slot */
+  HX_F_R2_PROCS,      /* [n_r2] */
+  HX_F_R2_COUNTS,     /* [n_r2] */
+  HX_F_R2_DISPLS,     /* [n_r2] */
+  HX_F_UNPACK_SRC,    /* [H]        slot of halo entry j in [stage-1 recv | stage-2 recv] */
+  HX_F_BT_PTR,        /* [n_local+1] transpose of the pack map: row -> slots */
+  HX_F_BT_PERM,       /* [E1]       send slots grouped by local row, ascending */
+  HX_F_COUNT
+} hx_field;
+/* Number of int32 elements of a field for a rank (HX_ERR_RANGE for a bad rank/field). */
+int hx_plan_field_size(const hx_plan* plan, int rank, hx_field field, int64_t* count);
+/* Copies a field to host memory dst (capacity given by hx_plan_field_size). */
+int hx_plan_field_copy(const hx_plan* plan, int rank, hx_field field, int32_t* dst);
+
+/* Persistent request for one rank of a plan (its arrays stay on the device).
+ * x_local device [n_local, ncols]; halo device [H, ncols]. */
+int hx_req_from_plan(const hx_plan* plan, int rank, const void* x_local, void* halo,
+                     hx_dtype dtype, int ncols, hx_req** out);
+
+/* ---------------------------------------------------------------------------
+ * Start / Wait -- Listing 4 (MPIX_Start, MPIX_Wait).
+ *
+ * hx_start: pack the stage-1 send arena from x_local (inactive -> active;
+ *   HX_ERR_STATE if already active).
+ * hx_wait: redistribution pack (locality variant) from the receive arena,
+ *   then unpack into the halo (active -> inactive).  Waiting on an inactive
+ *   request returns HX_SUCCESS and does nothing, as for an inactive
+ *   persistent MPI request.  Both calls only enqueue work on stream.
+ * The receive arena is filled by the (not built) transport between Start and
+ * Wait; callers simulate it by writing into hx_req_arena(HX_ARENA_RECV).
+ * ------------------------------------------------------------------------- */
+int hx_start(hx_req* req, void* stream);
+int hx_wait(hx_req* req, void* stream);
+
+enum { HX_ARENA_SEND = 0, HX_ARENA_RECV = 1 };
+/* Device pointer and row count of a request's arena.  Send arena layout:
+ * [stage-1 send (E1) | stage-2 send (E2)]; receive arena:
+ * [stage-1 recv (R1) | stage-2 recv (R2)]; rows of ncols values. */
+int hx_req_arena(hx_req* req, int which, void** dev_ptr, int64_t* rows);
+
+/* Backward of the pack (the differentiable path): for every local row i,
+ * g_x[i] = sum over stage-1 send slots k packed from row i, in ascending k, of
+ * g_send[k]; adds only, in the request's dtype, first term first (a lone
+ * -0.0 stays -0.0), rows never packed get +0.0.  g_send device [E1, ncols],
+ * g_x device [n_local, ncols]; bound persistently. */
+int hx_req_bind_grad(hx_req* req, const void* g_send, void* g_x);
+int hx_backward(hx_req* req, void* stream);
+int hx_req_free(hx_req** req);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many persistent requests driven as one (one persistent kernel per
+ * phase, captured in a hipGraph at init and replayed by start/wait).
+ *
+ * hx_batch_init: members are existing requests (same dtype and ncols); they
+ *   stay owned by the caller and must outlive the batch.  sched NULL = use a
+ *   cached tuned schedule for this shape if one exists, else the default.
+ * hx_batch_from_plan: every rank of a plan as one batch over flat arrays
+ *   ("world").  x_global device [n, ncols]; halo_all device [sum H, ncols]
+ *   (ranks in order).  With flags & HX_WORLD_SIM_TRANSFER, start also copies
+ *   each stage-1 message into its receiver's arena and wait copies each
+ *   stage-2 message likewise (the simulated transport; not part of the
+ *   path's own work).  The world's backward is the full adjoint of the
+ *   exchange: g_x[c] = sum over ranks s (ascending) whose halo holds c of
+ *   g_halo_all at that entry, fixed order as hx_backward.
+ * hx_batch_start / hx_batch_wait: Start / Wait of all members (graph launch).
+ * hx_batch_start_plain / hx_batch_wait_plain: the same work as one launch per
+ *   member (the plain one-plan-per-launch form, for comparison).
+ * hx_batch_tune: times candidate schedules on the batch's own buffers (the
+ *   candidates write the same arenas/halos a start/wait would), keeps the
+ *   fastest, re-captures the graphs, and records it in the tuning cache
+ *   (file named by HX_TUNE_CACHE, if set).
+ * ------------------------------------------------------------------------- */
+enum { HX_WORLD_SIM_TRANSFER = 1 };
+int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, hx_batch** out);
+int hx_batch_from_plan(const hx_plan* plan, const void* x_global, void* halo_all,
+                       hx_dtype dtype, int ncols, int flags, const hx_sched* sched,
+                       hx_batch** out);
+int hx_batch_start(hx_batch* b, void* stream);
+int hx_batch_wait(hx_batch* b, void* stream);
+int hx_batch_start_plain(hx_batch* b, void* stream);
+int hx_batch_wait_plain(hx_batch* b, void* stream);
+/* Backward: member batches use each member's bound gradients; worlds use
+ * g_in = g_halo_all [sum H, ncols] and g_out = g_x_global [n, ncols]. */
+int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out);
+int hx_batch_backward(hx_batch* b, void* stream);
+int hx_batch_backward_plain(hx_batch* b, void* stream);
+int hx_batch_tune(hx_batch* b, void* stream);
+/* The schedule in use for a phase (0 pack, 1 redistribution, 2 unpack, 3 backward). */
+int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out);
+/* World arenas: which = HX_ARENA_SEND / HX_ARENA_RECV, all ranks concatenated
+ * as [stage-1 part of every rank | stage-2 part of every rank].
+ * hx_batch_arena_offset gives the first row of a rank's stage-1 part
+ * (which = HX_ARENA_SEND / HX_ARENA_RECV) or stage-2 part (which | 2);
+ * rank = nranks gives the end of the part. */
+int hx_batch_arena(hx_batch* b, int which, void** dev_ptr, int64_t* rows);
+int hx_batch_arena_offset(hx_batch* b, int which, int rank, int64_t* row_offset);
+/* Algorithmic bytes moved per phase launch (phase as in hx_batch_get_sched):
+ * each read of a distinct source row, each output row written, each index. */
+int hx_batch_bytes(const hx_batch* b, int phase, int64_t* bytes);
+int hx_batch_free(hx_batch** b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HX_H */

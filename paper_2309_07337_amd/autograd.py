@@ -1,0 +1,64 @@
+"""Differentiable halo exchange over every rank of a plan.
+
+``HaloExchange`` binds a whole-decomposition batch (all ranks on this GPU)
+to persistent buffers; ``HaloGather`` is the ``torch.autograd.Function``
+whose forward runs Start/Wait of all ranks (pack, simulated transfer,
+redistribution, unpack) and whose backward runs the library's fixed-order
+transpose sum: for every owned row c, the gradient is the sum over the ranks
+whose halo holds c, in ascending rank order, of that halo entry's gradient.
+Both directions run in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+
+class HaloExchange:
+    """Persistent exchange of ``x_global [n, ncols] -> halo_all [sum H, ncols]``.
+
+    The buffers are allocated once (persistent semantics): the forward output
+    aliases ``self.halo`` and is overwritten by the next forward.
+    """
+
+    def __init__(self, plan: L.Plan, n: int, halo_rows: int, ncols: int, dtype=torch.float32,
+                 device="cuda", sim_transfer: bool = True, sched=None):
+        self.x = torch.zeros(n, ncols, dtype=dtype, device=device)
+        self.halo = torch.zeros(halo_rows, ncols, dtype=dtype, device=device)
+        self.g_halo = torch.zeros_like(self.halo)
+        self.g_x = torch.zeros_like(self.x)
+        flags = L.HX_WORLD_SIM_TRANSFER if sim_transfer else 0
+        self.batch = L.hx_batch_from_plan(plan, self.x, self.halo, flags=flags, sched=sched)
+        L.hx_batch_bind_grad(self.batch, self.g_halo, self.g_x)
+
+    def forward(self, stream=None) -> torch.Tensor:
+        L.hx_batch_start(self.batch, stream)
+        L.hx_batch_wait(self.batch, stream)
+        return self.halo
+
+    def backward(self, stream=None) -> torch.Tensor:
+        L.hx_batch_backward(self.batch, stream)
+        return self.g_x
+
+
+class HaloGather(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, ex: HaloExchange):
+        if x.data_ptr() != ex.x.data_ptr():
+            ex.x.copy_(x)
+        ex.forward()
+        ctx.ex = ex
+        return ex.halo.detach()
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        ex: HaloExchange = ctx.ex
+        if g.data_ptr() != ex.g_halo.data_ptr() or not g.is_contiguous():
+            ex.g_halo.copy_(g)
+        ex.backward()
+        return ex.g_x.clone(), None
+
+
+def halo_gather(x: torch.Tensor, ex: HaloExchange) -> torch.Tensor:
+    return HaloGather.apply(x, ex)

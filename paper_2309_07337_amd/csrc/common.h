@@ -1,0 +1,123 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "hx.h"
+
+namespace hx {
+
+// ---------------------------------------------------------------------------
+// Errors: thread-local last message / last HIP error.
+// ---------------------------------------------------------------------------
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define HX_HIP(call)                                                  \
+  do {                                                                \
+    hipError_t hx_e_ = (call);                                        \
+    if (hx_e_ != hipSuccess) return ::hx::hip_fail(hx_e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define HX_TRY(call)                 \
+  do {                               \
+    int hx_rc_ = (call);             \
+    if (hx_rc_ != HX_SUCCESS) return hx_rc_; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory owned by library objects.
+// ---------------------------------------------------------------------------
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevMem() { release(); }
+  void release();
+  int alloc(size_t nbytes);  // frees previous contents; zero bytes -> nullptr
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+int upload(DevMem& dst, const void* host, size_t bytes);
+template <class T>
+int upload_vec(DevMem& dst, const std::vector<T>& v) {
+  return upload(dst, v.data(), v.size() * sizeof(T));
+}
+
+int device_cus();  // number of compute units of the current device
+
+// ---------------------------------------------------------------------------
+// Kernels' work descriptions.
+// ---------------------------------------------------------------------------
+// dst[r, :] = src[idx ? idx[r] : r, :] for r < nrows (rows of row_bytes).
+struct GatherJob {
+  const char* src;
+  char* dst;
+  const int32_t* idx;
+  int64_t nrows;
+};
+// out[i, :] = in[idx[ptr[i]], :] + in[idx[ptr[i]+1], :] + ... (ascending,
+// first term first; empty -> +0) for i < nrows.
+struct SegSumJob {
+  const char* in;
+  char* out;
+  const int32_t* ptr;
+  const int32_t* idx;
+  int64_t nrows;
+};
+
+enum JobKind { KIND_GATHER = 0, KIND_SEGSUM = 1 };
+
+struct Sched {
+  int tile_rows = 0;
+  int block_threads = 0;
+  int blocks_per_cu = 0;
+  int nontemporal = 0;
+  int per_neighbor = 0;
+};
+Sched default_sched(int kind, int row_bytes);
+Sched resolve_sched(const hx_sched* s, int kind, int row_bytes);
+hx_sched to_public(const Sched& s);
+
+// A prepared launch: jobs and their tile prefix in device memory, plus the
+// launch shape.  Launch reads the tables at run time, so a captured graph
+// stays valid as long as the table lives.
+struct LaunchTable {
+  int kind = KIND_GATHER;
+  int dtype = HX_F64;
+  int row_bytes = 0;
+  int vec_bytes = 0;  // 16, 8 or 4: divides row_bytes and all base pointers
+  Sched sched;
+  int njobs = 0;
+  int64_t ntiles = 0;
+  int grid = 0;
+  DevMem jobs;        // GatherJob[] or SegSumJob[]
+  DevMem tile_start;  // int64_t[njobs + 1]
+  bool empty() const { return ntiles == 0; }
+};
+
+int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_bytes,
+                       const Sched& s, LaunchTable* t);
+int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes,
+                       const Sched& s, LaunchTable* t);
+int launch_table(const LaunchTable& t, hipStream_t stream);
+
+// Split a gather job per message (per neighbor) using the message counts.
+void split_gather_by_counts(const GatherJob& j, const std::vector<int32_t>& counts,
+                            size_t row_bytes, std::vector<GatherJob>* out);
+
+inline size_t dtype_bytes(int dtype) { return dtype == HX_F32 ? 4 : 8; }
+
+}  // namespace hx

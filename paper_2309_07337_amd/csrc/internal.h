@@ -1,0 +1,115 @@
+// Definitions of the opaque handles and internal entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "common.h"
+
+namespace hx {
+enum Phase { PH_PACK = 0, PH_REDIST = 1, PH_UNPACK = 2, PH_BWD = 3 };
+}
+
+// One rank's persistent request (rank-local arrays on the device).
+struct hx_req {
+  int dtype = HX_F64;
+  int ncols = 1;
+  size_t row_bytes = 8;
+  int variant = HX_PLAIN;
+  int rank = 0;
+  int64_t n_local = 0, H = 0, E1 = 0, E2 = 0, R1 = 0, R2 = 0;
+  const char* x = nullptr;
+  char* halo = nullptr;
+  bool unpack_identity = true;
+  std::vector<int32_t> s1_counts, s2_counts, r1_counts;  // message sizes (per-neighbor schedules)
+  hx::DevMem s1_idx, s2_src, unpack_src, bt_ptr, bt_perm;
+  hx::DevMem send, recv;  // [E1 | E2] and [R1 | R2] rows
+  int64_t U_pack = 0, U_redist = 0;  // distinct source rows of the pack / redistribution
+  int64_t bytes[4] = {0, 0, 0, 0};
+  const char* g_send = nullptr;
+  char* g_x = nullptr;
+  bool active = false;
+  bool tables_built = false;
+  hx::LaunchTable lt[4];
+};
+
+// Plan of a whole decomposition: per-rank arrays stored flat on the device,
+// with host copies of the per-rank offsets of every field.
+struct hx_plan {
+  int R = 0;
+  int ppn = 1;
+  int variant = HX_PLAIN;
+  int64_t n = 0;
+  std::vector<int64_t> row_starts;               // host [R+1]
+  std::vector<int64_t> off[HX_F_COUNT];          // host [R+1] per field
+  hx::DevMem d[HX_F_COUNT];                      // device int32 flat arrays
+  hx::DevMem row_starts_d;                       // device int64 [R+1]
+  std::vector<int64_t> r1_off, r2_off;           // host [R+1]: receive-arena row offsets
+  // totals
+  int64_t tot(int f) const { return off[f].empty() ? 0 : off[f].back(); }
+  int64_t size(int f, int r) const { return off[f][r + 1] - off[f][r]; }
+};
+
+struct hx_batch {
+  bool world = false;
+  int dtype = HX_F64;
+  int ncols = 1;
+  size_t row_bytes = 8;
+  int flags = 0;
+  std::vector<hx_req*> members;
+  hx::Sched sched[4];
+  hx::LaunchTable lt[4];
+  std::vector<hx::LaunchTable> plain[4];
+  bool plain_built[4] = {false, false, false, false};
+  hx::LaunchTable lt_xfer[2];
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  bool has_graph[3] = {false, false, false};
+  bool active = false;
+  int64_t bytes[4] = {0, 0, 0, 0};
+  int64_t bwd_rows_captured = 0;
+  // world (all ranks of a plan over flat arrays)
+  int R = 0;
+  int64_t n = 0;
+  const char* x_global = nullptr;
+  char* halo_all = nullptr;
+  const char* g_in = nullptr;
+  char* g_out = nullptr;
+  std::vector<int64_t> row_starts, s1_off, s2_off, r1_off, r2_off, halo_off;
+  int64_t E1_tot = 0, E2_tot = 0, R1_tot = 0, R2_tot = 0, H_tot = 0;
+  bool unpack_identity = true;
+  hx::DevMem send_all, recv_all;             // [S1 | S2], [RECV1 | RECV2] of all ranks
+  hx::DevMem gidx_pack, gidx_redist, gidx_unpack, gidx_x1, gidx_x2;
+  hx::DevMem wb_ptr, wb_idx;                 // adjoint CSR: global column -> halo_all rows
+  ~hx_batch();
+};
+
+namespace hx {
+int req_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<GatherJob>* g,
+             std::vector<SegSumJob>* s);
+void req_compute_bytes(hx_req* r);
+void batch_destroy_graphs(hx_batch* b);
+int batch_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged,
+                     std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s);
+int batch_build_table(const hx_batch* b, int phase, const Sched& sc, LaunchTable* t);
+int batch_build_plain(hx_batch* b, int phase);
+int batch_prepare(hx_batch* b);
+int batch_run_start(hx_batch* b, hipStream_t s);
+int batch_run_wait(hx_batch* b, hipStream_t s);
+int batch_init_scheds(hx_batch* b, const hx_sched* sched);
+int world_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged,
+                     std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s);
+
+// Device helpers implemented in plan.hip.
+int dev_exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);  // out[n] = total
+// HX_ERR_RANGE unless every idx[i] is in [0, hi).
+int dev_check_range(const int32_t* idx, int64_t n, int64_t hi, const char* what, hipStream_t s);
+int dev_count_nonzero_flags(const int32_t* idx, int64_t n, int64_t domain, int64_t* distinct,
+                            hipStream_t s);
+// Stable grouping of entries by key: for each key k in [0, nkeys), the
+// entries e with keys[e] == k in ascending e.  ptr [nkeys+1], perm [n].
+int dev_group_by_key(const int32_t* keys, int64_t n, int64_t nkeys, int32_t* ptr, int32_t* perm,
+                     hipStream_t s);
+}  // namespace hx

@@ -1,0 +1,811 @@
+// Host runtime of the C ABI: errors, device memory, topology handles,
+// persistent requests (init / Start / Wait / backward), batches captured in
+// hipGraphs, the plain one-launch-per-member form, and the schedule tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+namespace hx {
+
+namespace {
+thread_local std::string g_msg;
+thread_local int g_hip = 0;
+}  // namespace
+
+int fail(int code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_msg = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  g_hip = (int)e;
+  char buf[1024];
+  snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  g_msg = buf;
+  return e == hipErrorOutOfMemory ? HX_ERR_NOMEM : HX_ERR_HIP;
+}
+
+void DevMem::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+int DevMem::alloc(size_t nbytes) {
+  release();
+  if (nbytes == 0) return HX_SUCCESS;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    g_hip = (int)e;
+    return fail(HX_ERR_NOMEM, "hipMalloc(%zu) failed: %s", nbytes, hipGetErrorString(e));
+  }
+  bytes = nbytes;
+  return HX_SUCCESS;
+}
+
+int upload(DevMem& dst, const void* host, size_t bytes) {
+  HX_TRY(dst.alloc(bytes));
+  if (bytes) HX_HIP(hipMemcpy(dst.p, host, bytes, hipMemcpyHostToDevice));
+  return HX_SUCCESS;
+}
+
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
+Sched default_sched(int kind, int row_bytes) {
+  Sched s;
+  s.block_threads = 256;
+  s.blocks_per_cu = 8;
+  s.nontemporal = 0;
+  s.per_neighbor = 0;
+  // about 32 KiB of output per tile
+  int rows = std::max(64, (32 << 10) / std::max(row_bytes, 1));
+  rows = std::min(rows, 8192);
+  if (kind == KIND_SEGSUM) rows = std::max(64, rows / 2);
+  s.tile_rows = rows;
+  return s;
+}
+
+Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
+  Sched s = default_sched(kind, row_bytes);
+  if (!p) return s;
+  if (p->tile_rows > 0) s.tile_rows = p->tile_rows;
+  if (p->block_threads > 0) s.block_threads = p->block_threads;
+  if (p->blocks_per_cu > 0) s.blocks_per_cu = p->blocks_per_cu;
+  s.nontemporal = p->nontemporal ? 1 : 0;
+  s.per_neighbor = p->per_neighbor ? 1 : 0;
+  return s;
+}
+
+hx_sched to_public(const Sched& s) {
+  hx_sched o;
+  o.tile_rows = s.tile_rows;
+  o.block_threads = s.block_threads;
+  o.blocks_per_cu = s.blocks_per_cu;
+  o.nontemporal = s.nontemporal;
+  o.per_neighbor = s.per_neighbor;
+  return o;
+}
+
+}  // namespace hx
+
+using namespace hx;
+
+// ===========================================================================
+// Topology
+// ===========================================================================
+struct hx_topo {
+  int rank = 0, nranks = 0;
+  std::vector<int> recv_procs, send_procs;
+};
+
+static int check_procs(int rank, int nranks, int n, const int* procs, const char* what) {
+  if (n < 0) return fail(HX_ERR_ARG, "%s: negative neighbor count", what);
+  if (n > 0 && !procs) return fail(HX_ERR_ARG, "%s: null neighbor list", what);
+  std::vector<int> v(procs, procs + n);
+  for (int p : v)
+    if (p < 0 || p >= nranks || p == rank)
+      return fail(HX_ERR_RANGE, "%s: neighbor %d out of range or self", what, p);
+  std::sort(v.begin(), v.end());
+  if (std::adjacent_find(v.begin(), v.end()) != v.end())
+    return fail(HX_ERR_RANGE, "%s: duplicate neighbor", what);
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_topo_create(int rank, int nranks, int n_recvs, const int* recv_procs,
+                              const int* recv_weights, int n_sends, const int* send_procs,
+                              const int* send_weights, int reorder, hx_topo** out) {
+  (void)recv_weights;
+  (void)send_weights;
+  if (!out) return fail(HX_ERR_ARG, "null out");
+  *out = nullptr;
+  if (nranks <= 0 || rank < 0 || rank >= nranks) return fail(HX_ERR_ARG, "bad rank/nranks");
+  if (reorder != 0) return fail(HX_ERR_UNSUPPORTED, "reorder is not supported (ranks are fixed)");
+  HX_TRY(check_procs(rank, nranks, n_recvs, recv_procs, "recv_procs"));
+  HX_TRY(check_procs(rank, nranks, n_sends, send_procs, "send_procs"));
+  auto* t = new (std::nothrow) hx_topo;
+  if (!t) return fail(HX_ERR_NOMEM, "out of host memory");
+  t->rank = rank;
+  t->nranks = nranks;
+  t->recv_procs.assign(recv_procs, recv_procs + n_recvs);
+  t->send_procs.assign(send_procs, send_procs + n_sends);
+  *out = t;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_topo_free(hx_topo** t) {
+  if (!t) return HX_SUCCESS;
+  delete *t;
+  *t = nullptr;
+  return HX_SUCCESS;
+}
+
+// ===========================================================================
+// Requests
+// ===========================================================================
+static int req_phase_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<GatherJob>* g,
+                          std::vector<SegSumJob>* s);
+
+static int build_req_tables(hx_req* r) {
+  if (r->tables_built) return HX_SUCCESS;
+  for (int ph = 0; ph < 4; ++ph) {
+    std::vector<GatherJob> g;
+    std::vector<SegSumJob> s;
+    HX_TRY(req_phase_jobs(r, ph, false, &g, &s));
+    const int kind = ph == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
+    const Sched sc = default_sched(kind, (int)r->row_bytes);
+    if (ph == PH_BWD) {
+      if (!s.empty()) HX_TRY(build_segsum_table(s, r->dtype, (int)r->row_bytes, sc, &r->lt[ph]));
+    } else {
+      HX_TRY(build_gather_table(g, r->dtype, (int)r->row_bytes, sc, &r->lt[ph]));
+    }
+  }
+  r->tables_built = true;
+  return HX_SUCCESS;
+}
+
+static int req_phase_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<GatherJob>* g,
+                          std::vector<SegSumJob>* s) {
+  const size_t rb = r->row_bytes;
+  switch (phase) {
+    case PH_PACK: {
+      GatherJob j{r->x, r->send.as<char>(), r->s1_idx.as<int32_t>(), r->E1};
+      if (per_nbr) split_gather_by_counts(j, r->s1_counts, rb, g);
+      else g->push_back(j);
+      break;
+    }
+    case PH_REDIST: {
+      GatherJob j{r->recv.as<char>(), r->send.as<char>() + r->E1 * (int64_t)rb, r->s2_src.as<int32_t>(),
+                  r->E2};
+      if (per_nbr) split_gather_by_counts(j, r->s2_counts, rb, g);
+      else g->push_back(j);
+      break;
+    }
+    case PH_UNPACK: {
+      GatherJob j{r->recv.as<char>(), r->halo, r->unpack_identity ? nullptr : r->unpack_src.as<int32_t>(),
+                  r->H};
+      if (per_nbr && r->unpack_identity) split_gather_by_counts(j, r->r1_counts, rb, g);
+      else g->push_back(j);
+      break;
+    }
+    case PH_BWD: {
+      if (r->g_x && (r->g_send || r->E1 == 0))
+        s->push_back(SegSumJob{r->g_send, r->g_x, r->bt_ptr.as<int32_t>(), r->bt_perm.as<int32_t>(),
+                               r->n_local});
+      break;
+    }
+    default:
+      return fail(HX_ERR_ARG, "bad phase");
+  }
+  return HX_SUCCESS;
+}
+
+int hx::req_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<GatherJob>* g,
+                 std::vector<SegSumJob>* s) {
+  return req_phase_jobs(r, phase, per_nbr, g, s);
+}
+
+static int64_t count_distinct_host(const std::vector<int32_t>& idx, int64_t domain) {
+  if (idx.empty() || domain <= 0) return 0;
+  std::vector<uint8_t> seen((size_t)domain, 0);
+  int64_t u = 0;
+  for (int32_t v : idx)
+    if (v >= 0 && v < domain && !seen[v]) { seen[v] = 1; ++u; }
+  return u;
+}
+
+void hx::req_compute_bytes(hx_req* r) {
+  const int64_t rb = (int64_t)r->row_bytes;
+  r->bytes[PH_PACK] = (r->E1 + r->U_pack) * rb + 4 * r->E1;
+  r->bytes[PH_REDIST] = (r->E2 + r->U_redist) * rb + 4 * r->E2;
+  r->bytes[PH_UNPACK] = 2 * r->H * rb + (r->unpack_identity ? 0 : 4 * r->H);
+  r->bytes[PH_BWD] = (r->E1 + r->n_local) * rb + 4 * (r->E1 + r->n_local + 1);
+}
+
+// Builds the transpose of the pack map (rows -> send slots, ascending slot)
+// on the host for list-initialised requests.
+static void host_transpose(const std::vector<int32_t>& idx, int64_t n_local, std::vector<int32_t>* ptr,
+                           std::vector<int32_t>* perm) {
+  ptr->assign((size_t)n_local + 1, 0);
+  for (int32_t v : idx) (*ptr)[(size_t)v + 1]++;
+  for (int64_t i = 0; i < n_local; ++i) (*ptr)[(size_t)i + 1] += (*ptr)[(size_t)i];
+  std::vector<int32_t> fill(ptr->begin(), ptr->end() - 1);
+  perm->assign(idx.size(), 0);
+  for (size_t k = 0; k < idx.size(); ++k) (*perm)[(size_t)fill[(size_t)idx[k]]++] = (int32_t)k;
+}
+
+static int check_layout(int n, const int* counts, const int* displs, int64_t* total, const char* what) {
+  if (n > 0 && !counts) return fail(HX_ERR_ARG, "%s: null counts", what);
+  int64_t acc = 0;
+  for (int i = 0; i < n; ++i) {
+    if (counts[i] < 0) return fail(HX_ERR_ARG, "%s: negative count", what);
+    if (displs && displs[i] != acc)
+      return fail(HX_ERR_ARG, "%s: displacement %d of neighbor %d is not the packed prefix %lld", what,
+                  displs[i], i, (long long)acc);
+    acc += counts[i];
+  }
+  if (acc >= INT32_MAX) return fail(HX_ERR_UNSUPPORTED, "%s: more than 2^31 rows", what);
+  *total = acc;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local, const int* sendcounts,
+                                          const int* sdispls, const int* send_idx, void* halo,
+                                          const int* recvcounts, const int* rdispls, hx_dtype dtype,
+                                          int ncols, const hx_topo* topo, hx_req** out) {
+  if (!out) return fail(HX_ERR_ARG, "null out");
+  *out = nullptr;
+  if (!topo) return fail(HX_ERR_ARG, "null topology");
+  if (dtype != HX_F32 && dtype != HX_F64) return fail(HX_ERR_ARG, "bad dtype");
+  if (ncols <= 0) return fail(HX_ERR_ARG, "ncols must be positive");
+  if (n_local < 0) return fail(HX_ERR_ARG, "negative n_local");
+  if (n_local >= INT32_MAX) return fail(HX_ERR_UNSUPPORTED, "n_local beyond 2^31 rows");
+  int64_t E = 0, H = 0;
+  HX_TRY(check_layout((int)topo->send_procs.size(), sendcounts, sdispls, &E, "send"));
+  HX_TRY(check_layout((int)topo->recv_procs.size(), recvcounts, rdispls, &H, "recv"));
+  if (E > 0 && !send_idx) return fail(HX_ERR_ARG, "null send_idx");
+  if (E > 0 && !x_local) return fail(HX_ERR_ARG, "null x_local");
+  if (H > 0 && !halo) return fail(HX_ERR_ARG, "null halo");
+  for (int64_t k = 0; k < E; ++k)
+    if (send_idx[k] < 0 || send_idx[k] >= n_local)
+      return fail(HX_ERR_RANGE, "send_idx[%lld] = %d outside [0, %lld)", (long long)k, send_idx[k],
+                  (long long)n_local);
+  std::unique_ptr<hx_req> r(new (std::nothrow) hx_req);
+  if (!r) return fail(HX_ERR_NOMEM, "out of host memory");
+  r->dtype = dtype;
+  r->ncols = ncols;
+  r->row_bytes = (size_t)ncols * dtype_bytes(dtype);
+  r->variant = HX_PLAIN;
+  r->rank = topo->rank;
+  r->n_local = n_local;
+  r->E1 = E;
+  r->E2 = 0;
+  r->R1 = H;
+  r->R2 = 0;
+  r->H = H;
+  r->x = static_cast<const char*>(x_local);
+  r->halo = static_cast<char*>(halo);
+  r->unpack_identity = true;
+  std::vector<int32_t> idx(send_idx, send_idx + E);
+  r->s1_counts.assign(sendcounts, sendcounts + topo->send_procs.size());
+  r->r1_counts.assign(recvcounts, recvcounts + topo->recv_procs.size());
+  std::vector<int32_t> ptr, perm;
+  host_transpose(idx, n_local, &ptr, &perm);
+  HX_TRY(upload_vec(r->s1_idx, idx));
+  HX_TRY(upload_vec(r->bt_ptr, ptr));
+  HX_TRY(upload_vec(r->bt_perm, perm));
+  HX_TRY(r->send.alloc((size_t)E * r->row_bytes));
+  HX_TRY(r->recv.alloc((size_t)H * r->row_bytes));
+  r->U_pack = count_distinct_host(idx, n_local);
+  r->U_redist = 0;
+  req_compute_bytes(r.get());
+  *out = r.release();
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_start(hx_req* r, void* stream) {
+  if (!r) return fail(HX_ERR_ARG, "null request");
+  if (r->active) return fail(HX_ERR_STATE, "request already active");
+  HX_TRY(build_req_tables(r));
+  HX_TRY(launch_table(r->lt[PH_PACK], (hipStream_t)stream));
+  r->active = true;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_wait(hx_req* r, void* stream) {
+  if (!r) return fail(HX_ERR_ARG, "null request");
+  if (!r->active) return HX_SUCCESS;
+  HX_TRY(build_req_tables(r));
+  HX_TRY(launch_table(r->lt[PH_REDIST], (hipStream_t)stream));
+  HX_TRY(launch_table(r->lt[PH_UNPACK], (hipStream_t)stream));
+  r->active = false;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_req_arena(hx_req* r, int which, void** dev_ptr, int64_t* rows) {
+  if (!r || !dev_ptr || !rows) return fail(HX_ERR_ARG, "null argument");
+  if (which == HX_ARENA_SEND) {
+    *dev_ptr = r->send.p;
+    *rows = r->E1 + r->E2;
+  } else if (which == HX_ARENA_RECV) {
+    *dev_ptr = r->recv.p;
+    *rows = r->R1 + r->R2;
+  } else {
+    return fail(HX_ERR_ARG, "bad arena id");
+  }
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_req_bind_grad(hx_req* r, const void* g_send, void* g_x) {
+  if (!r) return fail(HX_ERR_ARG, "null request");
+  if ((r->E1 > 0 && !g_send) || (r->n_local > 0 && !g_x)) return fail(HX_ERR_ARG, "null gradient buffer");
+  r->g_send = static_cast<const char*>(g_send);
+  r->g_x = static_cast<char*>(g_x);
+  r->lt[PH_BWD] = LaunchTable();
+  std::vector<GatherJob> g;
+  std::vector<SegSumJob> s;
+  HX_TRY(req_phase_jobs(r, PH_BWD, false, &g, &s));
+  HX_TRY(build_segsum_table(s, r->dtype, (int)r->row_bytes, default_sched(KIND_SEGSUM, (int)r->row_bytes),
+                            &r->lt[PH_BWD]));
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_backward(hx_req* r, void* stream) {
+  if (!r) return fail(HX_ERR_ARG, "null request");
+  if (!r->g_x && r->n_local > 0) return fail(HX_ERR_STATE, "no gradient buffers bound");
+  return launch_table(r->lt[PH_BWD], (hipStream_t)stream);
+}
+
+extern "C" int hx_req_free(hx_req** r) {
+  if (!r) return HX_SUCCESS;
+  delete *r;
+  *r = nullptr;
+  return HX_SUCCESS;
+}
+
+// ===========================================================================
+// Batches
+// ===========================================================================
+namespace {
+
+int capture_graph(hipStream_t cap, const std::function<int(hipStream_t)>& body, hipGraphExec_t* exec,
+                  bool* has) {
+  *has = false;
+  HX_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  int rc = body(cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cap, &g);
+  if (rc != HX_SUCCESS) {
+    if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  HX_HIP(e);
+  size_t nn = 0;
+  (void)hipGraphGetNodes(g, nullptr, &nn);
+  if (nn == 0) {
+    (void)hipGraphDestroy(g);
+    return HX_SUCCESS;
+  }
+  hipError_t ie = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HX_HIP(ie);
+  *has = true;
+  return HX_SUCCESS;
+}
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string s = p.gcnArchName;
+  auto c = s.find(':');
+  return c == std::string::npos ? s : s.substr(0, c);
+}
+
+int ilog2(int64_t v) {
+  int l = 0;
+  while (v > 1) { v >>= 1; ++l; }
+  return l;
+}
+
+std::mutex g_cache_mu;
+
+}  // namespace
+
+void hx::batch_destroy_graphs(hx_batch* b) {
+  for (int i = 0; i < 3; ++i) {
+    if (b->has_graph[i]) (void)hipGraphExecDestroy(b->graph[i]);
+    b->has_graph[i] = false;
+  }
+}
+
+hx_batch::~hx_batch() {
+  batch_destroy_graphs(this);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+}
+
+int hx::batch_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged,
+                         std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s) {
+  g->clear();
+  s->clear();
+  if (b->world) return world_phase_jobs(b, phase, per_nbr, merged, g, s);
+  for (hx_req* r : b->members) {
+    std::vector<GatherJob> gj;
+    std::vector<SegSumJob> sj;
+    HX_TRY(req_phase_jobs(r, phase, per_nbr, &gj, &sj));
+    g->push_back(gj);
+    s->push_back(sj);
+  }
+  return HX_SUCCESS;
+}
+
+// Batched launch table of a phase under a schedule (all members' jobs).
+int hx::batch_build_table(const hx_batch* b, int phase, const Sched& sc, LaunchTable* t) {
+  std::vector<std::vector<GatherJob>> g;
+  std::vector<std::vector<SegSumJob>> s;
+  HX_TRY(batch_phase_jobs(b, phase, sc.per_neighbor != 0, true, &g, &s));
+  *t = LaunchTable();
+  if (phase == PH_BWD) {
+    std::vector<SegSumJob> all;
+    for (auto& v : s) all.insert(all.end(), v.begin(), v.end());
+    return build_segsum_table(all, b->dtype, (int)b->row_bytes, sc, t);
+  }
+  std::vector<GatherJob> all;
+  for (auto& v : g) all.insert(all.end(), v.begin(), v.end());
+  return build_gather_table(all, b->dtype, (int)b->row_bytes, sc, t);
+}
+
+int hx::batch_build_plain(hx_batch* b, int phase) {
+  b->plain[phase].clear();
+  std::vector<std::vector<GatherJob>> g;
+  std::vector<std::vector<SegSumJob>> s;
+  HX_TRY(batch_phase_jobs(b, phase, false, false, &g, &s));
+  const int kind = phase == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
+  const Sched sc = default_sched(kind, (int)b->row_bytes);
+  const size_t nm = phase == PH_BWD ? s.size() : g.size();
+  b->plain[phase].resize(nm);
+  for (size_t m = 0; m < nm; ++m) {
+    if (phase == PH_BWD) HX_TRY(build_segsum_table(s[m], b->dtype, (int)b->row_bytes, sc, &b->plain[phase][m]));
+    else HX_TRY(build_gather_table(g[m], b->dtype, (int)b->row_bytes, sc, &b->plain[phase][m]));
+  }
+  b->plain_built[phase] = true;
+  return HX_SUCCESS;
+}
+
+// (Re)builds the batched tables for the current schedules and captures the
+// start / wait / backward graphs.
+int hx::batch_prepare(hx_batch* b) {
+  batch_destroy_graphs(b);
+  if (!b->world) {
+    b->bwd_rows_captured = 0;
+    for (hx_req* r : b->members) b->bwd_rows_captured += (r->g_x ? r->n_local : 0);
+  }
+  for (int ph = 0; ph < 4; ++ph) HX_TRY(batch_build_table(b, ph, b->sched[ph], &b->lt[ph]));
+  if (!b->cap_stream) HX_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  HX_TRY(capture_graph(b->cap_stream, [&](hipStream_t s) { return batch_run_start(b, s); }, &b->graph[0],
+                       &b->has_graph[0]));
+  HX_TRY(capture_graph(b->cap_stream, [&](hipStream_t s) { return batch_run_wait(b, s); }, &b->graph[1],
+                       &b->has_graph[1]));
+  HX_TRY(capture_graph(b->cap_stream, [&](hipStream_t s) { return launch_table(b->lt[PH_BWD], s); },
+                       &b->graph[2], &b->has_graph[2]));
+  return HX_SUCCESS;
+}
+
+int hx::batch_run_start(hx_batch* b, hipStream_t s) {
+  HX_TRY(launch_table(b->lt[PH_PACK], s));
+  if (b->world && (b->flags & HX_WORLD_SIM_TRANSFER)) HX_TRY(launch_table(b->lt_xfer[0], s));
+  return HX_SUCCESS;
+}
+
+int hx::batch_run_wait(hx_batch* b, hipStream_t s) {
+  HX_TRY(launch_table(b->lt[PH_REDIST], s));
+  if (b->world && (b->flags & HX_WORLD_SIM_TRANSFER)) HX_TRY(launch_table(b->lt_xfer[1], s));
+  HX_TRY(launch_table(b->lt[PH_UNPACK], s));
+  return HX_SUCCESS;
+}
+
+static std::string cache_key(const hx_batch* b, int phase) {
+  std::ostringstream k;
+  int64_t rows = 0;
+  int njobs = 0;
+  std::vector<std::vector<GatherJob>> g;
+  std::vector<std::vector<SegSumJob>> s;
+  if (batch_phase_jobs(b, phase, false, true, &g, &s) == HX_SUCCESS) {
+    for (auto& v : g) for (auto& j : v) { rows += j.nrows; ++njobs; }
+    for (auto& v : s) for (auto& j : v) { rows += j.nrows; ++njobs; }
+  }
+  k << arch_name() << "|p" << phase << "|t" << b->dtype << "|rb" << b->row_bytes << "|r" << ilog2(rows + 1)
+    << "|j" << ilog2(njobs + 1) << "|w" << (b->world ? 1 : 0);
+  return k.str();
+}
+
+static const char* cache_path() { return std::getenv("HX_TUNE_CACHE"); }
+
+static bool cache_lookup(const std::string& key, Sched* out) {
+  const char* path = cache_path();
+  if (!path) return false;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  std::ifstream f(path);
+  std::string k;
+  Sched s;
+  bool found = false;
+  while (f >> k >> s.tile_rows >> s.block_threads >> s.blocks_per_cu >> s.nontemporal >> s.per_neighbor) {
+    if (k == key) { *out = s; found = true; }
+  }
+  return found;
+}
+
+static void cache_store(const std::string& key, const Sched& s) {
+  const char* path = cache_path();
+  if (!path) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  std::ofstream f(path, std::ios::app);
+  f << key << ' ' << s.tile_rows << ' ' << s.block_threads << ' ' << s.blocks_per_cu << ' ' << s.nontemporal
+    << ' ' << s.per_neighbor << '\n';
+}
+
+int hx::batch_init_scheds(hx_batch* b, const hx_sched* sched) {
+  for (int ph = 0; ph < 4; ++ph) {
+    const int kind = ph == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
+    if (sched) {
+      b->sched[ph] = resolve_sched(sched, kind, (int)b->row_bytes);
+    } else {
+      Sched s;
+      b->sched[ph] = cache_lookup(cache_key(b, ph), &s) ? s : default_sched(kind, (int)b->row_bytes);
+    }
+  }
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, hx_batch** out) {
+  if (!out) return fail(HX_ERR_ARG, "null out");
+  *out = nullptr;
+  if (n <= 0 || !reqs) return fail(HX_ERR_ARG, "empty batch");
+  for (int i = 0; i < n; ++i) {
+    if (!reqs[i]) return fail(HX_ERR_ARG, "null member %d", i);
+    if (reqs[i]->dtype != reqs[0]->dtype || reqs[i]->ncols != reqs[0]->ncols)
+      return fail(HX_ERR_ARG, "members differ in dtype or ncols");
+  }
+  std::unique_ptr<hx_batch> b(new (std::nothrow) hx_batch);
+  if (!b) return fail(HX_ERR_NOMEM, "out of host memory");
+  b->world = false;
+  b->dtype = reqs[0]->dtype;
+  b->ncols = reqs[0]->ncols;
+  b->row_bytes = reqs[0]->row_bytes;
+  b->members.assign(reqs, reqs + n);
+  for (int ph = 0; ph < 4; ++ph) {
+    b->bytes[ph] = 0;
+    for (hx_req* r : b->members) b->bytes[ph] += r->bytes[ph];
+  }
+  HX_TRY(batch_init_scheds(b.get(), sched));
+  HX_TRY(batch_prepare(b.get()));
+  *out = b.release();
+  return HX_SUCCESS;
+}
+
+static int launch_graph(hx_batch* b, int which, hipStream_t s) {
+  if (!b->has_graph[which]) return HX_SUCCESS;
+  HX_HIP(hipGraphLaunch(b->graph[which], s));
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_start(hx_batch* b, void* stream) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (b->active) return fail(HX_ERR_STATE, "batch already active");
+  HX_TRY(launch_graph(b, 0, (hipStream_t)stream));
+  b->active = true;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_wait(hx_batch* b, void* stream) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (!b->active) return HX_SUCCESS;
+  HX_TRY(launch_graph(b, 1, (hipStream_t)stream));
+  b->active = false;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_start_plain(hx_batch* b, void* stream) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (b->active) return fail(HX_ERR_STATE, "batch already active");
+  hipStream_t s = (hipStream_t)stream;
+  if (!b->plain_built[PH_PACK]) HX_TRY(batch_build_plain(b, PH_PACK));
+  for (auto& t : b->plain[PH_PACK]) HX_TRY(launch_table(t, s));
+  if (b->world && (b->flags & HX_WORLD_SIM_TRANSFER)) HX_TRY(launch_table(b->lt_xfer[0], s));
+  b->active = true;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_wait_plain(hx_batch* b, void* stream) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (!b->active) return HX_SUCCESS;
+  hipStream_t s = (hipStream_t)stream;
+  if (!b->plain_built[PH_REDIST]) HX_TRY(batch_build_plain(b, PH_REDIST));
+  if (!b->plain_built[PH_UNPACK]) HX_TRY(batch_build_plain(b, PH_UNPACK));
+  for (auto& t : b->plain[PH_REDIST]) HX_TRY(launch_table(t, s));
+  if (b->world && (b->flags & HX_WORLD_SIM_TRANSFER)) HX_TRY(launch_table(b->lt_xfer[1], s));
+  for (auto& t : b->plain[PH_UNPACK]) HX_TRY(launch_table(t, s));
+  b->active = false;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (!b->world) return fail(HX_ERR_ARG, "member batches use each member's hx_req_bind_grad");
+  if (!g_in || !g_out) return fail(HX_ERR_ARG, "null gradient buffer");
+  b->g_in = static_cast<const char*>(g_in);
+  b->g_out = static_cast<char*>(g_out);
+  b->plain_built[PH_BWD] = false;
+  return batch_prepare(b);
+}
+
+extern "C" int hx_batch_backward(hx_batch* b, void* stream) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (b->world && !b->g_out) return fail(HX_ERR_STATE, "no gradient buffers bound");
+  if (!b->world) {
+    // member gradients may have been bound after the batch was created
+    int64_t rows = 0;
+    for (hx_req* r : b->members) rows += (r->g_x ? r->n_local : 0);
+    if (rows != b->bwd_rows_captured) {
+      b->bwd_rows_captured = rows;
+      b->plain_built[PH_BWD] = false;
+      HX_TRY(batch_prepare(b));
+    }
+  }
+  return launch_graph(b, 2, (hipStream_t)stream);
+}
+
+extern "C" int hx_batch_backward_plain(hx_batch* b, void* stream) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (!b->plain_built[PH_BWD]) HX_TRY(batch_build_plain(b, PH_BWD));
+  for (auto& t : b->plain[PH_BWD]) HX_TRY(launch_table(t, (hipStream_t)stream));
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out) {
+  if (!b || !out || phase < 0 || phase > 3) return fail(HX_ERR_ARG, "bad argument");
+  *out = to_public(b->sched[phase]);
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_bytes(const hx_batch* b, int phase, int64_t* bytes) {
+  if (!b || !bytes || phase < 0 || phase > 3) return fail(HX_ERR_ARG, "bad argument");
+  *bytes = b->bytes[phase];
+  return HX_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// Tuner: times candidate schedules for each phase on the batch's buffers.
+// ---------------------------------------------------------------------------
+static int time_table(const LaunchTable& t, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, float* best) {
+  HX_TRY(launch_table(t, s));  // warm-up
+  *best = 1e30f;
+  for (int i = 0; i < reps; ++i) {
+    HX_HIP(hipEventRecord(e0, s));
+    HX_TRY(launch_table(t, s));
+    HX_HIP(hipEventRecord(e1, s));
+    HX_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    HX_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *best = std::min(*best, ms);
+  }
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (b->active) return fail(HX_ERR_STATE, "batch is active");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HX_HIP(hipEventCreate(&e0));
+  HX_HIP(hipEventCreate(&e1));
+  int rc = HX_SUCCESS;
+  for (int ph = 0; ph < 4 && rc == HX_SUCCESS; ++ph) {
+    if (b->lt[ph].empty()) continue;
+    const int kind = ph == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
+    const int rb = (int)b->row_bytes;
+    std::vector<Sched> cands;
+    const int base = default_sched(kind, rb).tile_rows;
+    for (int tf : {1, 2, 4, 8, 16, 32})
+      for (int bpc : {2, 4, 8})
+        for (int bt : {256, 512})
+          for (int nt : {0, 1})
+            for (int pn : {0, 1}) {
+              if (pn && b->world) continue;
+              Sched c;
+              c.tile_rows = std::max(16, base * tf / 8);
+              c.block_threads = bt;
+              c.blocks_per_cu = bpc;
+              c.nontemporal = nt;
+              c.per_neighbor = pn;
+              cands.push_back(c);
+            }
+    Sched best = b->sched[ph];
+    float best_ms = 1e30f;
+    {
+      LaunchTable t;
+      rc = batch_build_table(b, ph, best, &t);
+      if (rc == HX_SUCCESS) rc = time_table(t, s, e0, e1, 3, &best_ms);
+    }
+    for (const Sched& c : cands) {
+      if (rc != HX_SUCCESS) break;
+      LaunchTable t;
+      rc = batch_build_table(b, ph, c, &t);
+      if (rc != HX_SUCCESS) break;
+      float ms = 0;
+      rc = time_table(t, s, e0, e1, 3, &ms);
+      if (rc == HX_SUCCESS && ms < best_ms * 0.98f) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    if (rc == HX_SUCCESS) {
+      b->sched[ph] = best;
+      cache_store(cache_key(b, ph), best);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HX_TRY(rc);
+  return batch_prepare(b);
+}
+
+extern "C" int hx_batch_free(hx_batch** b) {
+  if (!b) return HX_SUCCESS;
+  delete *b;
+  *b = nullptr;
+  return HX_SUCCESS;
+}
+
+// ===========================================================================
+// Errors / version
+// ===========================================================================
+extern "C" const char* hx_error_string(int code) {
+  switch (code) {
+    case HX_SUCCESS: return "success";
+    case HX_ERR_ARG: return "invalid argument";
+    case HX_ERR_RANGE: return "index out of range";
+    case HX_ERR_STATE: return "invalid request state";
+    case HX_ERR_NOMEM: return "out of memory";
+    case HX_ERR_UNSUPPORTED: return "unsupported";
+    case HX_ERR_HIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+extern "C" int hx_last_hip_error(void) { return g_hip; }
+extern "C" const char* hx_last_error_message(void) { return g_msg.c_str(); }
+extern "C" const char* hx_version(void) { return "hx 0.1 gfx950"; }

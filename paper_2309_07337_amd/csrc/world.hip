@@ -1,0 +1,434 @@
+// Requests and whole-decomposition batches ("worlds") built from a plan.
+//
+// A world keeps every rank's arenas in one flat allocation each:
+//   send_all = [stage-1 send of rank 0, 1, ... | stage-2 send of rank 0, 1, ...]
+//   recv_all = [stage-1 recv of rank 0, 1, ... | stage-2 recv of rank 0, 1, ...]
+// and turns each phase into one gather over global row indices, so a phase
+// of all ranks is a single launch.  The simulated transfer of a stage is one
+// more gather, from each sender's message segment into the receiver's slots.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <memory>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+namespace hx {
+namespace {
+
+constexpr int TB = 256;
+
+unsigned blocks_for(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + TB - 1) / TB, 1 << 16));
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ int upper_rank(const int64_t* __restrict__ starts, int R, int64_t v) {
+  int lo = 0, hi = R - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (starts[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Largest l in [a, b) with v[l] <= x (v ascending).
+__device__ __forceinline__ int64_t upper_in(const int32_t* __restrict__ v, int64_t a, int64_t b, int64_t x) {
+  int64_t lo = a, hi = b - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (v[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// out[k] = base[rank(k)] + in[k], rank(k) from the entry offsets.
+__global__ void k_add_rank_base(const int32_t* __restrict__ in, int64_t n, const int64_t* __restrict__ off, int R,
+                                const int64_t* __restrict__ base, int32_t* out) {
+  GRID_STRIDE(k, n) {
+    const int r = upper_rank(off, R, k);
+    out[k] = (int32_t)(base[r] + in[k]);
+  }
+}
+
+// Unpack map in world coordinates: slot u of rank r's [stage-1 | stage-2]
+// receive arena -> row of recv_all.
+__global__ void k_world_unpack(const int32_t* __restrict__ u, int64_t n, const int64_t* __restrict__ hoff, int R,
+                               const int64_t* __restrict__ r1_off, const int64_t* __restrict__ r2_off,
+                               int64_t R1_tot, int32_t* out) {
+  GRID_STRIDE(e, n) {
+    const int r = upper_rank(hoff, R, e);
+    const int64_t R1r = r1_off[r + 1] - r1_off[r];
+    const int64_t v = u[e];
+    out[e] = (int32_t)(v < R1r ? r1_off[r] + v : R1_tot + r2_off[r] + (v - R1r));
+  }
+}
+
+// Simulated transfer of one stage: for every receive slot, the row of the
+// sender's send arena holding it.  Receive lists (procs, displs, entry
+// offsets) of each rank and send lists of each rank, all ascending.
+__global__ void k_transfer_map(int64_t nslots, int R, const int64_t* __restrict__ roff,
+                               const int64_t* __restrict__ rp_off, const int32_t* __restrict__ r_procs,
+                               const int32_t* __restrict__ r_counts, const int32_t* __restrict__ r_displs,
+                               const int64_t* __restrict__ soff, const int64_t* __restrict__ sp_off,
+                               const int32_t* __restrict__ s_procs, const int32_t* __restrict__ s_counts,
+                               const int32_t* __restrict__ s_displs, int64_t send_base, int32_t* out,
+                               int* err) {
+  GRID_STRIDE(i, nslots) {
+    const int r = upper_rank(roff, R, i);
+    const int64_t il = i - roff[r];
+    if (rp_off[r + 1] <= rp_off[r]) {
+      atomicOr(err, 1);
+      out[i] = 0;
+      continue;
+    }
+    const int64_t l = upper_in(r_displs, rp_off[r], rp_off[r + 1], il);
+    const int q = r_procs[l];
+    const int64_t a = sp_off[q], b = sp_off[q + 1];
+    const int64_t pos = upper_in(s_procs, a, b, r);
+    if (b <= a || s_procs[pos] != r || s_counts[pos] != r_counts[l]) {
+      atomicOr(err, 1);
+      out[i] = 0;
+      continue;
+    }
+    out[i] = (int32_t)(send_base + soff[q] + s_displs[pos] + (il - r_displs[l]));
+  }
+}
+
+int check_err(const DevMem& err, const char* what) {
+  int h = 0;
+  HX_HIP(hipMemcpy(&h, err.p, sizeof h, hipMemcpyDeviceToHost));
+  if (h) return fail(HX_ERR_ARG, "%s: send and receive lists do not match", what);
+  return HX_SUCCESS;
+}
+
+}  // namespace
+
+int world_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged,
+                     std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s) {
+  (void)per_nbr;
+  const int64_t rb = (int64_t)b->row_bytes;
+  const char* sa = b->send_all.as<char>();
+  const char* ra = b->recv_all.as<char>();
+  switch (phase) {
+    case PH_PACK:
+      if (merged) {
+        g->push_back({GatherJob{b->x_global, (char*)sa, b->gidx_pack.as<int32_t>(), b->E1_tot}});
+      } else {
+        for (int r = 0; r < b->R; ++r)
+          g->push_back({GatherJob{b->x_global, (char*)sa + b->s1_off[r] * rb, b->gidx_pack.as<int32_t>() + b->s1_off[r],
+                                  b->s1_off[r + 1] - b->s1_off[r]}});
+      }
+      break;
+    case PH_REDIST:
+      if (merged) {
+        g->push_back({GatherJob{ra, (char*)sa + b->E1_tot * rb, b->gidx_redist.as<int32_t>(), b->E2_tot}});
+      } else {
+        for (int r = 0; r < b->R; ++r)
+          g->push_back({GatherJob{ra, (char*)sa + (b->E1_tot + b->s2_off[r]) * rb,
+                                  b->gidx_redist.as<int32_t>() + b->s2_off[r], b->s2_off[r + 1] - b->s2_off[r]}});
+      }
+      break;
+    case PH_UNPACK:
+      if (merged) {
+        g->push_back({GatherJob{ra, b->halo_all, b->unpack_identity ? nullptr : b->gidx_unpack.as<int32_t>(),
+                                b->H_tot}});
+      } else {
+        for (int r = 0; r < b->R; ++r) {
+          const int64_t h0 = b->halo_off[r], h = b->halo_off[r + 1] - h0;
+          if (b->unpack_identity)
+            g->push_back({GatherJob{ra + h0 * rb, b->halo_all + h0 * rb, nullptr, h}});
+          else
+            g->push_back({GatherJob{ra, b->halo_all + h0 * rb, b->gidx_unpack.as<int32_t>() + h0, h}});
+        }
+      }
+      break;
+    case PH_BWD:
+      if (!b->g_out) break;
+      if (merged) {
+        s->push_back({SegSumJob{b->g_in, b->g_out, b->wb_ptr.as<int32_t>(), b->wb_idx.as<int32_t>(), b->n}});
+      } else {
+        for (int r = 0; r < b->R; ++r) {
+          const int64_t r0 = b->row_starts[r];
+          s->push_back({SegSumJob{b->g_in, b->g_out + r0 * rb, b->wb_ptr.as<int32_t>() + r0, b->wb_idx.as<int32_t>(),
+                                  b->row_starts[r + 1] - r0}});
+        }
+      }
+      break;
+    default:
+      return fail(HX_ERR_ARG, "bad phase");
+  }
+  return HX_SUCCESS;
+}
+
+}  // namespace hx
+
+using namespace hx;
+
+// ===========================================================================
+// Per-rank request from a plan
+// ===========================================================================
+static int copy_slice(const hx_plan* p, int f, int rank, DevMem* dst) {
+  const int64_t c = p->size(f, rank);
+  HX_TRY(dst->alloc((size_t)c * 4));
+  if (c) HX_HIP(hipMemcpy(dst->p, p->d[f].as<int32_t>() + p->off[f][rank], (size_t)c * 4, hipMemcpyDeviceToDevice));
+  return HX_SUCCESS;
+}
+
+static int host_slice(const hx_plan* p, int f, int rank, std::vector<int32_t>* out) {
+  out->resize((size_t)p->size(f, rank));
+  if (!out->empty())
+    HX_HIP(hipMemcpy(out->data(), p->d[f].as<int32_t>() + p->off[f][rank], out->size() * 4, hipMemcpyDeviceToHost));
+  return HX_SUCCESS;
+}
+
+static int64_t distinct_count(const std::vector<int32_t>& v, int64_t domain) {
+  if (v.empty() || domain <= 0) return 0;
+  std::vector<uint8_t> seen((size_t)domain, 0);
+  int64_t u = 0;
+  for (int32_t x : v)
+    if (x >= 0 && x < domain && !seen[(size_t)x]) { seen[(size_t)x] = 1; ++u; }
+  return u;
+}
+
+extern "C" int hx_req_from_plan(const hx_plan* p, int rank, const void* x_local, void* halo, hx_dtype dtype,
+                                int ncols, hx_req** out) {
+  if (!out) return fail(HX_ERR_ARG, "null out");
+  *out = nullptr;
+  if (!p) return fail(HX_ERR_ARG, "null plan");
+  if (rank < 0 || rank >= p->R) return fail(HX_ERR_RANGE, "rank out of range");
+  if (dtype != HX_F32 && dtype != HX_F64) return fail(HX_ERR_ARG, "bad dtype");
+  if (ncols <= 0) return fail(HX_ERR_ARG, "ncols must be positive");
+  std::unique_ptr<hx_req> r(new (std::nothrow) hx_req);
+  if (!r) return fail(HX_ERR_NOMEM, "out of host memory");
+  r->dtype = dtype;
+  r->ncols = ncols;
+  r->row_bytes = (size_t)ncols * dtype_bytes(dtype);
+  r->variant = p->variant;
+  r->rank = rank;
+  r->n_local = p->row_starts[rank + 1] - p->row_starts[rank];
+  r->H = p->size(HX_F_HALO, rank);
+  r->E1 = p->size(HX_F_S1_IDX, rank);
+  r->E2 = p->size(HX_F_S2_SRC, rank);
+  r->R1 = p->r1_off[rank + 1] - p->r1_off[rank];
+  r->R2 = p->r2_off[rank + 1] - p->r2_off[rank];
+  if ((r->E1 > 0 && !x_local) || (r->H > 0 && !halo)) return fail(HX_ERR_ARG, "null vector or halo");
+  r->x = static_cast<const char*>(x_local);
+  r->halo = static_cast<char*>(halo);
+  r->unpack_identity = p->variant == HX_PLAIN;
+  HX_TRY(copy_slice(p, HX_F_S1_IDX, rank, &r->s1_idx));
+  HX_TRY(copy_slice(p, HX_F_S2_SRC, rank, &r->s2_src));
+  if (!r->unpack_identity) HX_TRY(copy_slice(p, HX_F_UNPACK_SRC, rank, &r->unpack_src));
+  HX_TRY(copy_slice(p, HX_F_BT_PTR, rank, &r->bt_ptr));
+  HX_TRY(copy_slice(p, HX_F_BT_PERM, rank, &r->bt_perm));
+  HX_TRY(host_slice(p, HX_F_S1_COUNTS, rank, &r->s1_counts));
+  HX_TRY(host_slice(p, HX_F_S2_COUNTS, rank, &r->s2_counts));
+  HX_TRY(host_slice(p, HX_F_R1_COUNTS, rank, &r->r1_counts));
+  std::vector<int32_t> s1, s2;
+  HX_TRY(host_slice(p, HX_F_S1_IDX, rank, &s1));
+  HX_TRY(host_slice(p, HX_F_S2_SRC, rank, &s2));
+  for (int32_t v : s1)
+    if (v < 0 || v >= r->n_local) return fail(HX_ERR_RANGE, "plan: pack index outside the rank's rows");
+  for (int32_t v : s2)
+    if (v < 0 || v >= r->R1) return fail(HX_ERR_RANGE, "plan: redistribution index outside stage-1 arena");
+  if (!r->unpack_identity) {
+    std::vector<int32_t> u;
+    HX_TRY(host_slice(p, HX_F_UNPACK_SRC, rank, &u));
+    for (int32_t v : u)
+      if (v < 0 || v >= r->R1 + r->R2) return fail(HX_ERR_RANGE, "plan: unpack index outside the arena");
+  } else if (r->R1 != r->H || r->R2 != 0) {
+    return fail(HX_ERR_ARG, "plain plan with a receive arena that is not the halo");
+  }
+  {
+    std::vector<int32_t> bp, bq;
+    HX_TRY(host_slice(p, HX_F_BT_PTR, rank, &bp));
+    HX_TRY(host_slice(p, HX_F_BT_PERM, rank, &bq));
+    if ((int64_t)bp.size() != r->n_local + 1 || bp.front() != 0 || bp.back() != r->E1)
+      return fail(HX_ERR_RANGE, "plan: transpose pointer array inconsistent");
+    for (size_t i = 1; i < bp.size(); ++i)
+      if (bp[i] < bp[i - 1]) return fail(HX_ERR_RANGE, "plan: transpose pointer array decreasing");
+    for (int32_t v : bq)
+      if (v < 0 || v >= r->E1) return fail(HX_ERR_RANGE, "plan: transpose entry outside the send arena");
+  }
+  r->U_pack = distinct_count(s1, r->n_local);
+  r->U_redist = distinct_count(s2, r->R1);
+  HX_TRY(r->send.alloc((size_t)(r->E1 + r->E2) * r->row_bytes));
+  HX_TRY(r->recv.alloc((size_t)(r->R1 + r->R2) * r->row_bytes));
+  req_compute_bytes(r.get());
+  *out = r.release();
+  return HX_SUCCESS;
+}
+
+// ===========================================================================
+// World batch
+// ===========================================================================
+extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* halo_all, hx_dtype dtype, int ncols,
+                                  int flags, const hx_sched* sched, hx_batch** out) {
+  if (!out) return fail(HX_ERR_ARG, "null out");
+  *out = nullptr;
+  if (!p) return fail(HX_ERR_ARG, "null plan");
+  if (dtype != HX_F32 && dtype != HX_F64) return fail(HX_ERR_ARG, "bad dtype");
+  if (ncols <= 0) return fail(HX_ERR_ARG, "ncols must be positive");
+  const int R = p->R;
+  std::unique_ptr<hx_batch> b(new (std::nothrow) hx_batch);
+  if (!b) return fail(HX_ERR_NOMEM, "out of host memory");
+  b->world = true;
+  b->dtype = dtype;
+  b->ncols = ncols;
+  b->row_bytes = (size_t)ncols * dtype_bytes(dtype);
+  b->flags = flags;
+  b->R = R;
+  b->n = p->n;
+  b->row_starts = p->row_starts;
+  b->s1_off = p->off[HX_F_S1_IDX];
+  b->s2_off = p->off[HX_F_S2_SRC];
+  b->r1_off = p->r1_off;
+  b->r2_off = p->r2_off;
+  b->halo_off = p->off[HX_F_HALO];
+  b->E1_tot = b->s1_off.back();
+  b->E2_tot = b->s2_off.back();
+  b->R1_tot = b->r1_off.back();
+  b->R2_tot = b->r2_off.back();
+  b->H_tot = b->halo_off.back();
+  b->unpack_identity = p->variant == HX_PLAIN;
+  if ((b->E1_tot > 0 && !x_global) || (b->H_tot > 0 && !halo_all)) return fail(HX_ERR_ARG, "null vector or halo");
+  if (b->E1_tot + b->E2_tot >= INT32_MAX || b->R1_tot + b->R2_tot >= INT32_MAX)
+    return fail(HX_ERR_UNSUPPORTED, "world arenas beyond 2^31 rows");
+  b->x_global = static_cast<const char*>(x_global);
+  b->halo_all = static_cast<char*>(halo_all);
+  const size_t rb = b->row_bytes;
+  hipStream_t s = nullptr;
+  HX_TRY(b->send_all.alloc((size_t)(b->E1_tot + b->E2_tot) * rb));
+  HX_TRY(b->recv_all.alloc((size_t)(b->R1_tot + b->R2_tot) * rb));
+
+  DevMem rs_d, s1o, s2o, r1o, r2o, ho, err;
+  HX_TRY(upload_vec(rs_d, b->row_starts));
+  HX_TRY(upload_vec(s1o, b->s1_off));
+  HX_TRY(upload_vec(s2o, b->s2_off));
+  HX_TRY(upload_vec(r1o, b->r1_off));
+  HX_TRY(upload_vec(r2o, b->r2_off));
+  HX_TRY(upload_vec(ho, b->halo_off));
+  HX_TRY(err.alloc(4));
+  HX_HIP(hipMemset(err.p, 0, 4));
+
+  // pack: x_global rows
+  HX_TRY(b->gidx_pack.alloc((size_t)b->E1_tot * 4));
+  if (b->E1_tot)
+    hipLaunchKernelGGL(k_add_rank_base, dim3(blocks_for(b->E1_tot)), dim3(TB), 0, s, p->d[HX_F_S1_IDX].as<int32_t>(),
+                       b->E1_tot, s1o.as<int64_t>(), R, rs_d.as<int64_t>(), b->gidx_pack.as<int32_t>());
+  // redistribution: rows of recv_all (stage-1 part of the forwarder)
+  HX_TRY(b->gidx_redist.alloc((size_t)b->E2_tot * 4));
+  if (b->E2_tot)
+    hipLaunchKernelGGL(k_add_rank_base, dim3(blocks_for(b->E2_tot)), dim3(TB), 0, s, p->d[HX_F_S2_SRC].as<int32_t>(),
+                       b->E2_tot, s2o.as<int64_t>(), R, r1o.as<int64_t>(), b->gidx_redist.as<int32_t>());
+  // unpack
+  if (!b->unpack_identity) {
+    HX_TRY(b->gidx_unpack.alloc((size_t)b->H_tot * 4));
+    if (b->H_tot)
+      hipLaunchKernelGGL(k_world_unpack, dim3(blocks_for(b->H_tot)), dim3(TB), 0, s,
+                         p->d[HX_F_UNPACK_SRC].as<int32_t>(), b->H_tot, ho.as<int64_t>(), R, r1o.as<int64_t>(),
+                         r2o.as<int64_t>(), b->R1_tot, b->gidx_unpack.as<int32_t>());
+  }
+  HX_HIP(hipGetLastError());
+  // simulated transfers
+  {
+    DevMem rp1, sp1, rp2, sp2;
+    HX_TRY(upload_vec(rp1, p->off[HX_F_R1_PROCS]));
+    HX_TRY(upload_vec(sp1, p->off[HX_F_S1_PROCS]));
+    HX_TRY(upload_vec(rp2, p->off[HX_F_R2_PROCS]));
+    HX_TRY(upload_vec(sp2, p->off[HX_F_S2_PROCS]));
+    HX_TRY(b->gidx_x1.alloc((size_t)b->R1_tot * 4));
+    HX_TRY(b->gidx_x2.alloc((size_t)b->R2_tot * 4));
+    if (b->R1_tot)
+      hipLaunchKernelGGL(k_transfer_map, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, b->R1_tot, R, r1o.as<int64_t>(),
+                         rp1.as<int64_t>(), p->d[HX_F_R1_PROCS].as<int32_t>(), p->d[HX_F_R1_COUNTS].as<int32_t>(),
+                         p->d[HX_F_R1_DISPLS].as<int32_t>(), s1o.as<int64_t>(), sp1.as<int64_t>(),
+                         p->d[HX_F_S1_PROCS].as<int32_t>(), p->d[HX_F_S1_COUNTS].as<int32_t>(),
+                         p->d[HX_F_S1_DISPLS].as<int32_t>(), (int64_t)0, b->gidx_x1.as<int32_t>(),
+                         err.as<int>());
+    if (b->R2_tot)
+      hipLaunchKernelGGL(k_transfer_map, dim3(blocks_for(b->R2_tot)), dim3(TB), 0, s, b->R2_tot, R, r2o.as<int64_t>(),
+                         rp2.as<int64_t>(), p->d[HX_F_R2_PROCS].as<int32_t>(), p->d[HX_F_R2_COUNTS].as<int32_t>(),
+                         p->d[HX_F_R2_DISPLS].as<int32_t>(), s2o.as<int64_t>(), sp2.as<int64_t>(),
+                         p->d[HX_F_S2_PROCS].as<int32_t>(), p->d[HX_F_S2_COUNTS].as<int32_t>(),
+                         p->d[HX_F_S2_DISPLS].as<int32_t>(), b->E1_tot, b->gidx_x2.as<int32_t>(),
+                         err.as<int>());
+    HX_HIP(hipGetLastError());
+    HX_HIP(hipDeviceSynchronize());
+    HX_TRY(check_err(err, "world transfer"));
+  }
+  // every index a kernel will follow stays inside its source
+  HX_TRY(dev_check_range(b->gidx_pack.as<int32_t>(), b->E1_tot, b->n, "pack map", s));
+  HX_TRY(dev_check_range(b->gidx_redist.as<int32_t>(), b->E2_tot, b->R1_tot, "redistribution map", s));
+  if (!b->unpack_identity)
+    HX_TRY(dev_check_range(b->gidx_unpack.as<int32_t>(), b->H_tot, b->R1_tot + b->R2_tot, "unpack map", s));
+  else if (b->R1_tot != b->H_tot || b->R2_tot != 0)
+    return fail(HX_ERR_ARG, "plain plan with a receive arena that is not the halo");
+  HX_TRY(dev_check_range(b->gidx_x1.as<int32_t>(), b->R1_tot, b->E1_tot, "stage-1 transfer", s));
+  HX_TRY(dev_check_range(b->gidx_x2.as<int32_t>(), b->R2_tot, b->E1_tot + b->E2_tot, "stage-2 transfer", s));
+  // adjoint CSR: global column -> rows of halo_all, ascending (= ascending rank)
+  HX_TRY(b->wb_ptr.alloc((size_t)(b->n + 1) * 4));
+  HX_TRY(b->wb_idx.alloc((size_t)b->H_tot * 4));
+  HX_TRY(dev_group_by_key(p->d[HX_F_HALO].as<int32_t>(), b->H_tot, b->n, b->wb_ptr.as<int32_t>(),
+                          b->wb_idx.as<int32_t>(), s));
+  // transfer launch tables
+  {
+    const Sched sc = default_sched(KIND_GATHER, (int)rb);
+    std::vector<GatherJob> x1{GatherJob{b->send_all.as<char>(), b->recv_all.as<char>(), b->gidx_x1.as<int32_t>(),
+                                        b->R1_tot}};
+    std::vector<GatherJob> x2{GatherJob{b->send_all.as<char>(), b->recv_all.as<char>() + b->R1_tot * (int64_t)rb,
+                                        b->gidx_x2.as<int32_t>(), b->R2_tot}};
+    HX_TRY(build_gather_table(x1, dtype, (int)rb, sc, &b->lt_xfer[0]));
+    HX_TRY(build_gather_table(x2, dtype, (int)rb, sc, &b->lt_xfer[1]));
+  }
+  // algorithmic bytes per phase
+  {
+    int64_t U1 = 0, U2 = 0;
+    HX_TRY(dev_count_nonzero_flags(b->gidx_pack.as<int32_t>(), b->E1_tot, b->n, &U1, s));
+    HX_TRY(dev_count_nonzero_flags(b->gidx_redist.as<int32_t>(), b->E2_tot, b->R1_tot + b->R2_tot, &U2, s));
+    const int64_t rbi = (int64_t)rb;
+    b->bytes[PH_PACK] = (b->E1_tot + U1) * rbi + 4 * b->E1_tot;
+    b->bytes[PH_REDIST] = (b->E2_tot + U2) * rbi + 4 * b->E2_tot;
+    b->bytes[PH_UNPACK] = 2 * b->H_tot * rbi + (b->unpack_identity ? 0 : 4 * b->H_tot);
+    b->bytes[PH_BWD] = (b->H_tot + b->n) * rbi + 4 * (b->H_tot + b->n + 1);
+  }
+  HX_TRY(batch_init_scheds(b.get(), sched));
+  HX_TRY(batch_prepare(b.get()));
+  *out = b.release();
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_arena(hx_batch* b, int which, void** dev_ptr, int64_t* rows) {
+  if (!b || !dev_ptr || !rows) return fail(HX_ERR_ARG, "null argument");
+  if (!b->world) return fail(HX_ERR_ARG, "not a world batch");
+  if (which == HX_ARENA_SEND) {
+    *dev_ptr = b->send_all.p;
+    *rows = b->E1_tot + b->E2_tot;
+  } else if (which == HX_ARENA_RECV) {
+    *dev_ptr = b->recv_all.p;
+    *rows = b->R1_tot + b->R2_tot;
+  } else {
+    return fail(HX_ERR_ARG, "bad arena id");
+  }
+  return HX_SUCCESS;
+}
+
+// Row offset of a rank's stage-1 part; its stage-2 part starts at
+// (total stage-1 rows + the offset returned for which | 2).
+extern "C" int hx_batch_arena_offset(hx_batch* b, int which, int rank, int64_t* row_offset) {
+  if (!b || !row_offset) return fail(HX_ERR_ARG, "null argument");
+  if (!b->world) return fail(HX_ERR_ARG, "not a world batch");
+  if (rank < 0 || rank > b->R) return fail(HX_ERR_RANGE, "rank out of range");
+  switch (which) {
+    case HX_ARENA_SEND: *row_offset = b->s1_off[rank]; break;
+    case HX_ARENA_RECV: *row_offset = b->r1_off[rank]; break;
+    case HX_ARENA_SEND | 2: *row_offset = b->E1_tot + b->s2_off[rank]; break;
+    case HX_ARENA_RECV | 2: *row_offset = b->R1_tot + b->r2_off[rank]; break;
+    default: return fail(HX_ERR_ARG, "bad arena id");
+  }
+  return HX_SUCCESS;
+}

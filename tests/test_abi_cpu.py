@@ -1,0 +1,106 @@
+"""The C-ABI library loads and exports every entry point of include/hx.h;
+host-side argument validation works without a GPU (no compute calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2309_07337_amd as P
+from paper_2309_07337_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "hx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = header_functions()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTED) == names
+
+
+def test_version_and_error_strings():
+    assert "gfx950" in P.hx_version()
+    assert P.hx_error_string(0) == "success"
+    assert P.hx_error_string(P.HX_ERR_STATE) == "invalid request state"
+    assert P.hx_error_string(12345) == "unknown error"
+
+
+def test_topology_validation():
+    with pytest.raises(P.HXError) as e:
+        P.hx_topo_create(0, 4, [1], [2], reorder=1)
+    assert e.value.code == P.HX_ERR_UNSUPPORTED
+    for bad in ([0], [4], [-1], [1, 1]):
+        with pytest.raises(P.HXError) as e:
+            P.hx_topo_create(0, 4, bad, [2])
+        assert e.value.code == P.HX_ERR_RANGE
+    with pytest.raises(P.HXError) as e:
+        P.hx_topo_create(5, 4, [1], [2])
+    assert e.value.code == P.HX_ERR_ARG
+    t = P.hx_topo_create(0, 4, [1, 3], [2], recv_weights=[1, 1], send_weights=[7])
+    t.free()
+    t.free()
+
+
+class FakeTensor:
+    """Shape/dtype/pointer stand-in: validation fails before any device call."""
+
+    def __init__(self, rows, ncols=1):
+        import torch
+        self.shape = (rows, ncols)
+        self.dtype = torch.float64
+
+    def dim(self):
+        return 2
+
+    def data_ptr(self):
+        return 4096
+
+
+@pytest.mark.parametrize("kind", ["displs", "range", "negative"])
+def test_init_validation_on_host(kind):
+    topo = P.hx_topo_create(1, 4, [0, 2], [0, 2])
+    x, halo = FakeTensor(10), FakeTensor(5)
+    sc, sd, idx = [2, 3], [0, 2], [0, 1, 2, 3, 4]
+    rc, rd = [2, 3], [0, 2]
+    if kind == "displs":
+        sd = [0, 3]
+        code = P.HX_ERR_ARG
+    elif kind == "range":
+        idx = [0, 1, 2, 3, 10]
+        code = P.HX_ERR_RANGE
+    else:
+        rc = [-1, 6]
+        code = P.HX_ERR_ARG
+    with pytest.raises(P.HXError) as e:
+        P.hx_neighbor_alltoallv_init(x, sc, sd, idx, halo, rc, rd, topo)
+    assert e.value.code == code
+
+
+def test_plan_validation_on_host():
+    with pytest.raises(P.HXError) as e:
+        P.hx_plan_from_halos(2, [0, 3, 2], 1, P.HX_PLAIN, [0, 0, 0], None, stream=0)
+    assert e.value.code == P.HX_ERR_ARG
+    with pytest.raises(P.HXError) as e:
+        P.hx_plan_from_halos(P.HX_PLAN_MAX_RANKS + 1, np.arange(P.HX_PLAN_MAX_RANKS + 2), 1, P.HX_PLAIN,
+                             np.zeros(P.HX_PLAN_MAX_RANKS + 2), None, stream=0)
+    assert e.value.code == P.HX_ERR_UNSUPPORTED
+    with pytest.raises(P.HXError) as e:
+        P.hx_plan_from_halos(2, [0, 2, 4], 0, P.HX_LOCALITY_2STEP, [0, 0, 0], None, stream=0)
+    assert e.value.code == P.HX_ERR_ARG
+
+
+def test_product_path_has_no_cpu_fallback(monkeypatch, tmp_path):
+    """With the library missing, loading fails loudly instead of falling back."""
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        L.load()

@@ -1,0 +1,129 @@
+"""Batched persistent launches (hipGraph) vs the plain one-launch-per-plan
+form vs the oracle, bit for bit, under several schedules and the tuner."""
+import numpy as np
+import pytest
+
+import paper_2309_07337_amd as P
+from oracle import move as OM
+from oracle import plan as OP
+from tests.gpu_util import bits_equal, dev, host, need_gpu, say
+from workloads import batched_plan, batched_plan_sizes, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+
+
+def build_members(nplans, cap, ncols, dtype):
+    import torch
+    h, k = batched_plan_sizes()
+    mem = []
+    for b in range(nplans):
+        hb = int(min(h[b], cap))
+        kb = int(min(k[b], hb))
+        lists = batched_plan(b, hb, kb)
+        x = dev(uniform_pm1(100 + b, hb * ncols).reshape(hb, ncols)).to(dtype)
+        halo = torch.full((hb, ncols), float("nan"), dtype=dtype, device="cuda")
+        topo = P.hx_topo_create(0, 4096, lists["procs"], lists["procs"])
+        req = P.hx_neighbor_alltoallv_init(x, lists["counts"], lists["displs"], lists["send_idx"], halo,
+                                           lists["counts"], lists["displs"], topo)
+        recv = dev(uniform_pm1(200 + b, hb * ncols).reshape(hb, ncols)).to(dtype)
+        P.req_arena_view(req, P.HX_ARENA_RECV, ncols, dtype).copy_(recv)
+        g_send = dev(uniform_pm1(300 + b, hb * ncols).reshape(hb, ncols)).to(dtype)
+        g_x = torch.full_like(x, float("nan"))
+        P.hx_req_bind_grad(req, g_send, g_x)
+        mem.append(dict(lists=lists, x=x, halo=halo, req=req, recv=recv, g_send=g_send, g_x=g_x, h=hb))
+    return mem
+
+
+def check_members(mem, ncols, dtype):
+    for m in mem:
+        send = host(P.req_arena_view(m["req"], P.HX_ARENA_SEND, ncols, dtype))
+        assert bits_equal(send, OM.pack(host(m["x"]), m["lists"]["send_idx"]))
+        assert bits_equal(host(m["halo"]), host(m["recv"]))
+        ptr, perm = OP.transpose_csr(m["lists"]["send_idx"], m["h"])
+        assert bits_equal(host(m["g_x"]), OM.pack_transpose(host(m["g_send"]), ptr, perm))
+
+
+def reset(mem):
+    for m in mem:
+        m["halo"].fill_(float("nan"))
+        m["g_x"].fill_(float("nan"))
+        P.req_arena_view(m["req"], P.HX_ARENA_SEND, m["x"].shape[1], m["x"].dtype).fill_(float("nan"))
+
+
+SCHEDS = [None,
+          dict(tile_rows=64, block_threads=256, blocks_per_cu=1),
+          dict(tile_rows=1000, block_threads=512, blocks_per_cu=3, nontemporal=1),
+          dict(tile_rows=4096, block_threads=256, blocks_per_cu=8, per_neighbor=1),
+          dict(tile_rows=17, block_threads=512, blocks_per_cu=2, nontemporal=1, per_neighbor=1)]
+
+
+@pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f32", 1), ("f64", 1), ("f32", 64)])
+def test_batch_graph_equals_plain_equals_oracle(dtype_name, ncols):
+    need_gpu()
+    import torch
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    say("batch", dtype_name, ncols)
+    mem = build_members(24, 20000, ncols, dtype)
+    reqs = [m["req"] for m in mem]
+    for sched in SCHEDS:
+        say("  sched", sched)
+        b = P.hx_batch_init(reqs, sched=sched)
+        reset(mem)
+        P.hx_batch_start(b)
+        P.hx_batch_wait(b)
+        P.hx_batch_backward(b)
+        check_members(mem, ncols, dtype)
+        for rep in range(2):      # graph replays with eager work in between
+            reset(mem)
+            torch.cuda.synchronize()
+            P.hx_batch_start(b)
+            P.hx_batch_wait(b)
+            P.hx_batch_backward(b)
+            check_members(mem, ncols, dtype)
+        reset(mem)
+        P.hx_batch_start_plain(b)
+        P.hx_batch_wait_plain(b)
+        P.hx_batch_backward_plain(b)
+        check_members(mem, ncols, dtype)
+        b.free()
+
+
+def test_tuner_keeps_results_and_caches(tmp_path, monkeypatch):
+    need_gpu()
+    import torch
+    monkeypatch.setenv("HX_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    mem = build_members(16, 30000, 16, torch.float64)
+    b = P.hx_batch_init([m["req"] for m in mem])
+    P.hx_batch_tune(b)
+    scheds = [P.hx_batch_get_sched(b, ph) for ph in range(4)]
+    reset(mem)
+    P.hx_batch_start(b)
+    P.hx_batch_wait(b)
+    P.hx_batch_backward(b)
+    check_members(mem, 16, torch.float64)
+    text = (tmp_path / "tune.txt").read_text()
+    assert "gfx950" in text and len(text.splitlines()) >= 3
+    # a new batch of the same shape picks the cached schedules up
+    b2 = P.hx_batch_init([m["req"] for m in mem])
+    assert [P.hx_batch_get_sched(b2, ph) for ph in range(4)] == scheds
+    assert all(P.hx_batch_bytes(b, ph) > 0 for ph in (0, 2, 3))
+
+
+def test_batch_state_machine():
+    need_gpu()
+    import torch
+    mem = build_members(3, 2000, 2, torch.float32)
+    b = P.hx_batch_init([m["req"] for m in mem])
+    P.hx_batch_wait(b)
+    P.hx_batch_start(b)
+    with pytest.raises(P.HXError) as e:
+        P.hx_batch_start(b)
+    assert e.value.code == P.HX_ERR_STATE
+    P.hx_batch_wait(b)
+    x64 = torch.zeros(4, 2, dtype=torch.float64, device="cuda")
+    topo = P.hx_topo_create(0, 2, [1], [1])
+    other = P.hx_neighbor_alltoallv_init(x64, [1], [0], [0], torch.zeros(1, 2, dtype=torch.float64, device="cuda"),
+                                         [1], [0], topo)
+    with pytest.raises(P.HXError) as e:
+        P.hx_batch_init([mem[0]["req"], other])
+    assert e.value.code == P.HX_ERR_ARG

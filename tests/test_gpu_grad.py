@@ -1,0 +1,145 @@
+"""Backward of the exchange: the library's fixed-order transpose sum vs the
+oracle (bit-exact) and vs central finite differences; the autograd Function."""
+import numpy as np
+import pytest
+
+import paper_2309_07337_amd as P
+from oracle import move as OM
+from oracle import plan as OP
+from tests.conftest import cached_grid3d, cached_random_rows
+from tests.gpu_util import bits_equal, dev, gpu_plan, host, need_gpu, say
+from tests.test_oracle_brute import CASES
+from workloads import random_small_csr, uniform_pm1, uniform_pm1_f32
+
+pytestmark = pytest.mark.gpu
+
+
+def exchange_for(rs, rp, cols, ppn, variant, ncols):
+    import torch
+    from paper_2309_07337_amd.autograd import HaloExchange
+    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    H = sum(int(P.hx_plan_field(plan, r, "halo").size) for r in range(len(rs) - 1))
+    return HaloExchange(plan, int(rs[-1]), H, ncols, dtype=torch.float32), plan
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("case", CASES[:6])
+def test_backward_tiny_bit_exact(case, variant):
+    need_gpu()
+    import torch
+    from paper_2309_07337_amd.autograd import halo_gather
+    n, R, mx, pf, seed, uneven, ppn = case
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    ex, _ = exchange_for(rs, rp, cols, ppn, variant, 3)
+    x = dev(uniform_pm1_f32(seed, n * 3).reshape(n, 3)).requires_grad_(True)
+    y = halo_gather(x, ex)
+    H = y.shape[0]
+    assert bits_equal(host(y), host(x)[np.concatenate(halos)] if H else np.zeros((0, 3), np.float32))
+    g = uniform_pm1_f32(seed + 9, H * 3).reshape(H, 3)
+    y.backward(dev(g))
+    gy = np.split(g, np.cumsum([h.size for h in halos])[:-1])
+    assert bits_equal(host(x.grad), OM.exchange_adjoint_reference(halos, gy, n))
+
+
+def test_backward_grid3d_64_columns():
+    """The 27-point decomposition with 64 FP32 features per row."""
+    need_gpu()
+    import torch
+    from paper_2309_07337_amd.autograd import halo_gather
+    rs, rp, cols = cached_grid3d()
+    halos = OP.all_halos(rp, cols, rs)
+    n = int(rs[-1])
+    C = 64
+    say("grad grid3d")
+    ex, _ = exchange_for(rs, rp, cols, 64, "plain", C)
+    x = dev(uniform_pm1_f32(1, n * C).reshape(n, C)).requires_grad_(True)
+    y = halo_gather(x, ex)
+    H = y.shape[0]
+    g = uniform_pm1_f32(2, H * C).reshape(H, C)
+    y.backward(dev(g))
+    gy = np.split(g, np.cumsum([h.size for h in halos])[:-1])
+    assert bits_equal(host(x.grad), OM.exchange_adjoint_reference(halos, gy, n))
+
+
+def test_backward_random_rows_sampled_rows():
+    """Full size (4096 ranks, 64 FP32 columns): rows sampled from every
+    fan-out class are recomputed one by one by the oracle's definition."""
+    need_gpu()
+    import torch
+    rs, rp, cols = cached_random_rows()
+    halos = OP.all_halos(rp, cols, rs)
+    n = int(rs[-1])
+    C = 64
+    say("grad random_rows")
+    ex, _ = exchange_for(rs, rp, cols, 128, "plain", C)
+    H = ex.halo.shape[0]
+    ex.x.copy_(dev(uniform_pm1_f32(5, n * C).reshape(n, C)))
+    y = ex.forward()
+    g = torch.empty_like(ex.g_halo)
+    step = 1 << 22
+    for lo in range(0, H, step):
+        hi = min(H, lo + step)
+        g[lo:hi] = dev(uniform_pm1_f32(6, (hi - lo) * C, start=lo * C).reshape(hi - lo, C))
+    ex.g_halo.copy_(g)
+    gx = ex.backward()
+    torch.cuda.synchronize()
+    allcols = np.concatenate(halos)
+    order = np.argsort(allcols, kind="stable")
+    counts = np.bincount(allcols, minlength=n)
+    ptr = np.concatenate([[0], np.cumsum(counts)])
+    rng = np.random.default_rng(0)
+    sample = []
+    for f in np.unique(counts):
+        rows = np.nonzero(counts == f)[0]
+        sample += rng.choice(rows, size=min(8, rows.size), replace=False).tolist()
+    gx_s = host(gx[torch.as_tensor(sample, device="cuda")])
+    for i, c in enumerate(sample):
+        pos = order[ptr[c]:ptr[c + 1]]
+        vals = host(g[torch.as_tensor(pos, device="cuda")]) if pos.size else np.zeros((0, C), np.float32)
+        want = OM.segmented_sum_fixed_order(vals, np.array([0, pos.size]), np.arange(pos.size))[0]
+        assert bits_equal(gx_s[i], want), (c, counts[c])
+    # forward at full size: sampled halo rows against the direct gather
+    idx = rng.choice(H, size=4096, replace=False)
+    xs = host(ex.x)
+    assert bits_equal(host(y[torch.as_tensor(idx, device="cuda")]), xs[allcols[idx]])
+
+
+def test_finite_differences():
+    """Central differences of L = sum(w * Y) (float64 on the device) at
+    h = 1e-3 in FP32, divided by the realised step, against the backward for
+    inputs drawn from every fan-out class: |g_fd - g| <= 1e-6 * max(1, |g|)."""
+    need_gpu()
+    import torch
+    from paper_2309_07337_amd.autograd import halo_gather
+    rs, rp, cols = cached_grid3d()
+    n = int(rs[-1])
+    C = 2
+    ex, plan = exchange_for(rs, rp, cols, 64, "plain", C)
+    x0 = dev(uniform_pm1_f32(3, n * C).reshape(n, C))
+    H = ex.halo.shape[0]
+    w = dev(uniform_pm1_f32(4, H * C).reshape(H, C)).double()
+    x = x0.clone().requires_grad_(True)
+    y = halo_gather(x, ex)
+    (y.double() * w).sum().backward()
+    grad = host(x.grad)
+    halos = [P.hx_plan_field(plan, r, "halo") for r in range(512)]
+    counts = np.bincount(np.concatenate(halos), minlength=n)
+    rng = np.random.default_rng(1)
+    picks = []
+    for f in np.unique(counts):
+        rows = np.nonzero(counts == f)[0]
+        picks += [(int(r), int(rng.integers(C))) for r in rng.choice(rows, size=min(4, rows.size), replace=False)]
+    h = np.float32(1e-3)
+    for (r, c) in picks:
+        v = float(x0[r, c])
+        vp, vm = np.float32(v) + h, np.float32(v) - h
+        losses = []
+        for val in (vp, vm):
+            xp = x0.clone()
+            xp[r, c] = float(val)
+            ex.x.copy_(xp)
+            losses.append(float((ex.forward().double() * w).sum()))
+        fd = (losses[0] - losses[1]) / (float(vp) - float(vm))
+        g = float(grad[r, c])
+        assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (r, c, counts[r], fd, g)

@@ -1,0 +1,137 @@
+"""GPU plan kernels vs the oracle, element for element (integer arrays: bit-exact).
+
+Covers halo discovery, owner segmentation (receive lists), the send-list
+transpose, the 2-step locality lists (node dedup, stage-1 aggregated
+messages, redistribution lists, unpack map) and the transpose of the pack map.
+"""
+import numpy as np
+import pytest
+
+import paper_2309_07337_amd as P
+from oracle import plan as OP
+from tests.conftest import cached_grid2d, cached_grid3d, cached_random_rows
+from tests.gpu_util import assert_plan_equal, dev, gpu_plan, need_gpu, plan_rank, say
+from tests.test_oracle_brute import CASES
+from workloads import random_small_csr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("case", CASES)
+def test_tiny_decompositions(case, variant):
+    need_gpu()
+    n, R, mx, pf, seed, uneven, ppn = case
+    say("plan tiny", case, variant)
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    for r in range(R):
+        assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"rank {r}")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_more_random_shapes(seed):
+    need_gpu()
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(50, 3000))
+    R = int(rng.integers(2, 40))
+    ppn = int(rng.integers(1, 9))
+    say("plan random", seed, n, R, ppn)
+    rs, rp, cols = random_small_csr(n, R, int(rng.integers(1, 12)), float(rng.random()), 100 + seed,
+                                    bool(seed % 2))
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    for variant in ("plain", "locality"):
+        plan = gpu_plan(rs, rp, cols, ppn, variant)
+        for r in range(R):
+            assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"{variant} rank {r}")
+
+
+def test_grid2d_all_ranks():
+    need_gpu()
+    rs, rp, cols = cached_grid2d()
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, 4)
+    for variant in ("plain", "locality"):
+        say("plan grid2d", variant)
+        plan = gpu_plan(rs, rp, cols, 4, variant)
+        for r in range(16):
+            assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"{variant} rank {r}")
+
+
+def test_grid3d_all_ranks():
+    need_gpu()
+    rs, rp, cols = cached_grid3d()
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, 64)
+    for variant in ("plain", "locality"):
+        say("plan grid3d", variant)
+        plan = gpu_plan(rs, rp, cols, 64, variant)
+        for r in range(512):
+            assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"{variant} rank {r}")
+
+
+def test_random_rows_sampled_ranks():
+    """Full-size random workload: the ranks the oracle can afford, incl. the
+    one with the most neighbors, the first, the last and a few others."""
+    need_gpu()
+    rs, rp, cols = cached_random_rows()
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, 128)
+    sample = [0, 1, 127, 128, 1511, 2048, 3001, 4095]
+    for variant in ("plain", "locality"):
+        say("plan random_rows", variant)
+        plan = gpu_plan(rs, rp, cols, 128, variant)
+        for r in sample:
+            assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"{variant} rank {r}")
+        # every rank's halo, and the totals
+        allh = np.concatenate([P.hx_plan_field(plan, r, "halo") for r in range(4096)])
+        assert np.array_equal(allh, np.concatenate(halos))
+
+
+def test_from_halos_matches_from_csr_and_validates():
+    need_gpu()
+    rs, rp, cols = random_small_csr(300, 12, 6, 0.5, 77, False)
+    for variant in ("plain", "locality"):
+        a = gpu_plan(rs, rp, cols, 3, variant)
+        hs = [P.hx_plan_field(a, r, "halo") for r in range(12)]
+        hp = np.concatenate([[0], np.cumsum([h.size for h in hs])])
+        b = P.hx_plan_from_halos(12, rs, 3, 1 if variant == "locality" else 0, hp,
+                                 dev(np.concatenate(hs).astype(np.int32)))
+        for r in range(12):
+            assert_plan_equal(plan_rank(b, r), plan_rank(a, r), f"rank {r}")
+    hs = [P.hx_plan_field(a, r, "halo") for r in range(12)]
+    hp = np.concatenate([[0], np.cumsum([h.size for h in hs])])
+    flat = np.concatenate(hs).astype(np.int32)
+    j = int(np.argmax(np.diff(hp) > 2))
+    bad = flat.copy()
+    bad[hp[j]], bad[hp[j] + 1] = bad[hp[j] + 1], bad[hp[j]]      # not increasing
+    with pytest.raises(P.HXError) as e:
+        P.hx_plan_from_halos(12, rs, 3, 0, hp, dev(bad))
+    assert e.value.code == P.HX_ERR_RANGE
+    bad = flat.copy()
+    bad[hp[j]] = rs[j]                                          # owned by its own rank
+    with pytest.raises(P.HXError) as e:
+        P.hx_plan_from_halos(12, rs, 3, 0, hp, dev(np.sort(bad)))
+    assert e.value.code == P.HX_ERR_RANGE
+    bad = cols.copy()
+    bad[5] = 300                                                # column out of range
+    with pytest.raises(P.HXError) as e:
+        gpu_plan(rs, rp, bad, 3, "plain")
+    assert e.value.code == P.HX_ERR_RANGE
+
+
+def test_degenerate_decompositions():
+    need_gpu()
+    # one rank: no halo at all; empty ranks; a rank with no rows
+    for (n, R, uneven) in [(40, 1, False), (20, 6, True), (5, 5, False)]:
+        rs, rp, cols = random_small_csr(n, R, 4, 0.7, 9, uneven)
+        halos = OP.all_halos(rp, cols, rs)
+        for ppn in (1, 2, R):
+            D = OP.Decomposition(halos, rs, ppn)
+            for variant in ("plain", "locality"):
+                plan = gpu_plan(rs, rp, cols, ppn, variant)
+                for r in range(R):
+                    assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"n{n} R{R} ppn{ppn} r{r}")

@@ -1,0 +1,127 @@
+"""Persistent requests initialised from explicit lists (the paper's init call):
+pack / unpack / backward vs the oracle, bit for bit, plus the request state
+machine and edge cases."""
+import numpy as np
+import pytest
+
+import paper_2309_07337_amd as P
+from oracle import move as OM
+from oracle import plan as OP
+from tests.gpu_util import bits_equal, dev, host, need_gpu, say
+from workloads import batched_plan, batched_plan_sizes, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+
+
+def make_req(lists, n_local, ncols, dtype, seed):
+    import torch
+    x = dev(uniform_pm1(seed, n_local * ncols).reshape(n_local, ncols)).to(dtype)
+    H = int(np.sum(lists["counts"]))
+    halo = torch.full((H, ncols), float("nan"), dtype=dtype, device="cuda")
+    topo = P.hx_topo_create(0, 4096, lists["procs"], lists["procs"])
+    req = P.hx_neighbor_alltoallv_init(x, lists["counts"], lists["displs"], lists["send_idx"], halo,
+                                       lists["counts"], lists["displs"], topo)
+    return req, x, halo
+
+
+def small_plans(cap=6000):
+    h, k = batched_plan_sizes()
+    out = []
+    for b in (0, 1, 2, 5, 11, 40):
+        hb = int(min(h[b], cap))
+        kb = int(min(k[b], hb))
+        out.append((b, hb, batched_plan(b, hb, kb)))
+    return out
+
+
+@pytest.mark.parametrize("dtype_name,ncols", [("f64", 1), ("f32", 1), ("f64", 16), ("f32", 64),
+                                               ("f64", 3), ("f32", 5), ("f32", 2), ("f64", 64)])
+def test_list_request_pack_unpack_backward(dtype_name, ncols):
+    need_gpu()
+    import torch
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    for b, h, lists in small_plans():
+        say("req", dtype_name, ncols, "plan", b, h)
+        req, x, halo = make_req(lists, h, ncols, dtype, 500 + b)
+        # simulated peers: the receive arena holds what the neighbors sent
+        recv = dev(uniform_pm1(900 + b, h * ncols).reshape(h, ncols)).to(dtype)
+        P.req_arena_view(req, P.HX_ARENA_RECV, ncols, dtype).copy_(recv)
+        P.hx_start(req)
+        P.hx_wait(req)
+        send = P.req_arena_view(req, P.HX_ARENA_SEND, ncols, dtype)
+        assert bits_equal(host(send), OM.pack(host(x), lists["send_idx"]))
+        assert bits_equal(host(halo), host(recv))
+        # backward of the pack
+        g_send = dev(uniform_pm1(1300 + b, h * ncols).reshape(h, ncols)).to(dtype)
+        g_x = torch.full_like(x, float("nan"))
+        P.hx_req_bind_grad(req, g_send, g_x)
+        P.hx_backward(req)
+        ptr, perm = OP.transpose_csr(lists["send_idx"], h)
+        assert bits_equal(host(g_x), OM.pack_transpose(host(g_send), ptr, perm))
+        req.free()
+
+
+def test_state_machine_and_repeat():
+    need_gpu()
+    import torch
+    b, h, lists = small_plans()[1]
+    req, x, halo = make_req(lists, h, 4, torch.float32, 3)
+    P.hx_wait(req)                         # inactive: no-op
+    P.hx_start(req)
+    with pytest.raises(P.HXError) as e:
+        P.hx_start(req)
+    assert e.value.code == P.HX_ERR_STATE
+    P.hx_wait(req)
+    for it in range(3):                    # persistent: re-start with new values
+        x.copy_(dev(uniform_pm1(40 + it, h * 4).reshape(h, 4)).float())
+        P.hx_start(req)
+        P.hx_wait(req)
+        send = P.req_arena_view(req, P.HX_ARENA_SEND, 4, torch.float32)
+        assert bits_equal(host(send), OM.pack(host(x), lists["send_idx"]))
+
+
+def test_edge_cases():
+    need_gpu()
+    import torch
+    # no neighbors at all
+    topo = P.hx_topo_create(0, 2, [], [])
+    x = torch.zeros(7, 2, dtype=torch.float64, device="cuda")
+    req = P.hx_neighbor_alltoallv_init(x, [], [], [], None, [], [], topo)
+    P.hx_start(req)
+    P.hx_wait(req)
+    g_x = torch.full_like(x, 5.0)
+    P.hx_req_bind_grad(req, None, g_x)
+    P.hx_backward(req)
+    assert np.all(host(g_x) == 0.0) and not np.any(np.signbit(host(g_x)))
+    # zero-count neighbors, one row, a single value sent many times
+    topo = P.hx_topo_create(1, 5, [0, 2, 3, 4], [0, 2, 3, 4])
+    x = dev(np.array([[-0.0], [2.5]], np.float32))
+    counts, displs = [0, 3, 0, 1], [0, 0, 3, 3]
+    idx = [1, 0, 1, 0]
+    halo = torch.zeros(4, 1, dtype=torch.float32, device="cuda")
+    req = P.hx_neighbor_alltoallv_init(x, counts, displs, idx, halo, counts, displs, topo)
+    P.req_arena_view(req, P.HX_ARENA_RECV, 1, torch.float32).copy_(dev(np.arange(4, dtype=np.float32)[:, None]))
+    P.hx_start(req)
+    P.hx_wait(req)
+    assert host(P.req_arena_view(req, P.HX_ARENA_SEND, 1, torch.float32))[:, 0].tolist() == [2.5, -0.0, 2.5, -0.0]
+    assert host(halo)[:, 0].tolist() == [0, 1, 2, 3]
+    g_send = dev(np.array([[1.0], [-0.0], [2.0], [-0.0]], np.float32))
+    g_x = torch.full_like(x, 9.0)
+    P.hx_req_bind_grad(req, g_send, g_x)
+    P.hx_backward(req)
+    gx = host(g_x)[:, 0]
+    assert gx[1] == 3.0 and gx[0] == 0.0 and np.signbit(gx[0])   # -0 + -0 = -0
+
+
+def test_misaligned_and_bad_arguments():
+    need_gpu()
+    import torch
+    topo = P.hx_topo_create(0, 2, [1], [1])
+    x = torch.zeros(8, 1, dtype=torch.float64, device="cuda")
+    halo = torch.zeros(2, 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.HXError) as e:
+        P.hx_neighbor_alltoallv_init(x, [2], [0], [0, 8], halo, [2], [0], topo)
+    assert e.value.code == P.HX_ERR_RANGE
+    with pytest.raises(P.HXError) as e:
+        P.hx_neighbor_alltoallv_init(x, [2], [1], [0, 1], halo, [2], [0], topo)
+    assert e.value.code == P.HX_ERR_ARG

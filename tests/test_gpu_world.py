@@ -1,0 +1,140 @@
+"""Whole-decomposition exchange on one GPU (every rank's Start/Wait with the
+simulated transfer) vs the oracle; per-rank requests built from a GPU plan."""
+import numpy as np
+import pytest
+
+import paper_2309_07337_amd as P
+from oracle import move as OM
+from oracle import plan as OP
+from tests.conftest import cached_grid2d, cached_grid3d, cached_random_rows
+from tests.gpu_util import bits_equal, dev, gpu_plan, host, need_gpu, say
+from tests.test_oracle_brute import CASES
+from workloads import random_small_csr, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+
+
+def run_world(plan, x, H, plain_launch=False):
+    import torch
+    halo = torch.full((H, x.shape[1]), float("nan"), dtype=x.dtype, device="cuda")
+    b = P.hx_batch_from_plan(plan, x, halo, flags=P.HX_WORLD_SIM_TRANSFER)
+    if plain_launch:
+        P.hx_batch_start_plain(b)
+        P.hx_batch_wait_plain(b)
+    else:
+        P.hx_batch_start(b)
+        P.hx_batch_wait(b)
+    return b, halo
+
+
+def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, seed=11, full_stages=True):
+    import torch
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    R = len(rs) - 1
+    n = int(rs[-1])
+    xh = uniform_pm1(seed, n * ncols).reshape(n, ncols)
+    if dtype_name == "f32":
+        xh = xh.astype(np.float32)
+    x = dev(xh)
+    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    H = sum(h.size for h in halos)
+    for plain_launch in (False, True):
+        b, halo = run_world(plan, x, H, plain_launch)
+        got = host(halo)
+        ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
+        assert bits_equal(got, ref)
+        if full_stages:
+            plans = [D.plan(r, variant) for r in range(R)]
+            out = OM.forward_all(plans, xh, rs)
+            send = host(P.batch_arena_view(b, P.HX_ARENA_SEND, ncols, dtype))
+            recv = host(P.batch_arena_view(b, P.HX_ARENA_RECV, ncols, dtype))
+            for r in range(R):
+                s1 = P.hx_batch_arena_offset(b, P.HX_ARENA_SEND, r)
+                s2 = P.hx_batch_arena_offset(b, P.HX_ARENA_SEND | 2, r)
+                r1 = P.hx_batch_arena_offset(b, P.HX_ARENA_RECV, r)
+                r2 = P.hx_batch_arena_offset(b, P.HX_ARENA_RECV | 2, r)
+                e1, e2 = out["send1"][r].shape[0], out["send2"][r].shape[0]
+                q1, q2 = out["recv1"][r].shape[0], out["recv2"][r].shape[0]
+                assert bits_equal(send[s1:s1 + e1], out["send1"][r]), r
+                assert bits_equal(send[s2:s2 + e2], out["send2"][r]), r
+                assert bits_equal(recv[r1:r1 + q1], out["recv1"][r]), r
+                assert bits_equal(recv[r2:r2 + q2], out["recv2"][r]), r
+        b.free()
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("case", CASES)
+def test_world_tiny(case, variant):
+    need_gpu()
+    n, R, mx, pf, seed, uneven, ppn = case
+    say("world tiny", case, variant)
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    for ncols, dt in ((1, "f64"), (3, "f32"), (16, "f64")):
+        check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dt)
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+def test_world_grid2d(variant):
+    need_gpu()
+    say("world grid2d", variant)
+    rs, rp, cols = cached_grid2d()
+    check_world_against_oracle(rs, rp, cols, 4, variant, 1, "f64")
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+def test_world_grid3d(variant):
+    need_gpu()
+    say("world grid3d", variant)
+    rs, rp, cols = cached_grid3d()
+    check_world_against_oracle(rs, rp, cols, 64, variant, 1, "f64")
+    check_world_against_oracle(rs, rp, cols, 64, variant, 8, "f32", full_stages=False)
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_world_random_rows_full_size(dtype_name):
+    """4096 ranks, locality-aware: every halo equals the direct gather x[N_r]."""
+    need_gpu()
+    import torch
+    say("world random_rows", dtype_name)
+    rs, rp, cols = cached_random_rows()
+    halos = OP.all_halos(rp, cols, rs)
+    n = int(rs[-1])
+    xh = uniform_pm1(7337, n).reshape(n, 1)
+    if dtype_name == "f32":
+        xh = xh.astype(np.float32)
+    plan = gpu_plan(rs, rp, cols, 128, "locality")
+    H = sum(h.size for h in halos)
+    b, halo = run_world(plan, dev(xh), H)
+    assert bits_equal(host(halo), xh[np.concatenate(halos)])
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+def test_rank_requests_from_plan(variant):
+    """One rank's request (its arrays alone): the receive arena is filled with
+    what its peers send (oracle transfer), Wait produces the oracle's
+    redistribution buffer and halo."""
+    need_gpu()
+    import torch
+    rs, rp, cols = cached_grid3d()
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, 64)
+    plans = [D.plan(r, variant) for r in range(512)]
+    n = int(rs[-1])
+    C = 4
+    xh = uniform_pm1(21, n * C).reshape(n, C)
+    out = OM.forward_all(plans, xh, rs)
+    plan = gpu_plan(rs, rp, cols, 64, variant)
+    for r in (0, 219, 300, 511):
+        say("rank request", variant, r)
+        x_local = dev(xh[rs[r]:rs[r + 1]])
+        halo = torch.full((halos[r].size, C), float("nan"), dtype=torch.float64, device="cuda")
+        req = P.hx_req_from_plan(plan, r, x_local, halo)
+        P.req_arena_view(req, P.HX_ARENA_RECV, C, torch.float64).copy_(dev(out["arena"][r]))
+        P.hx_start(req)
+        P.hx_wait(req)
+        send = host(P.req_arena_view(req, P.HX_ARENA_SEND, C, torch.float64))
+        assert bits_equal(send, np.concatenate([out["send1"][r], out["send2"][r]]))
+        assert bits_equal(host(halo), out["halo"][r])
+        req.free()
