@@ -115,6 +115,28 @@ def setup_batched(args, torch, P):
                 keep=members)
 
 
+def setup_copy(args, torch, P):
+    """Calibration: one request whose only work is the identity unpack of a
+    1 GiB receive arena (a plain device copy of known size)."""
+    C, dt = 16, torch.float64
+    rows = (1 << 30) // (C * 8)
+    topo = P.hx_topo_create(0, 2, [1], [])
+    x = torch.zeros(1, C, dtype=dt, device="cuda")
+    halo = torch.empty(rows, C, dtype=dt, device="cuda")
+    req = P.hx_neighbor_alltoallv_init(x, [], [], [], halo, [rows], [0], topo)
+    P.req_arena_view(req, P.HX_ARENA_RECV, C, dt).copy_(torch.arange(rows * C, dtype=dt, device="cuda").view(rows, C))
+    g_x = torch.empty_like(x)
+    P.hx_req_bind_grad(req, None, g_x)
+    batch = P.hx_batch_init([req])
+    P.hx_batch_start(batch)
+    P.hx_batch_wait(batch)
+    torch.cuda.synchronize()
+    assert torch.equal(halo, P.req_arena_view(req, P.HX_ARENA_RECV, C, dt))
+    cfg = {"workload": "copy calibration: identity unpack of a 1 GiB arena (128 B rows)", "bytes_copied": rows * C * 8}
+    return dict(batch=batch, members=[req], host=[], dtype="f64", cfg=cfg, phases=(0, 2, 3),
+                keep=(req, x, halo, g_x, topo))
+
+
 def setup_world(args, torch, P, name):
     import numpy as np
     from workloads import equal_row_starts, grid2d_5pt, grid3d_27pt, random_rows, uniform_pm1, uniform_pm1_f32
@@ -236,7 +258,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched256",
-                    choices=["batched256", "random_rows", "grid3d", "grid2d", "diff64"])
+                    choices=["batched256", "random_rows", "grid3d", "grid2d", "diff64", "copy"])
     ap.add_argument("--plans", type=int, default=256)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -254,6 +276,9 @@ def main():
     with torch.cuda.stream(stream):
         if args.workload == "batched256":
             S = setup_batched(args, torch, P)
+        elif args.workload == "copy":
+            args.cpu_plans = 0
+            S = setup_copy(args, torch, P)
         else:
             args.cpu_plans = 0
             S = setup_world(args, torch, P, args.workload)
@@ -273,8 +298,8 @@ def main():
     dom = max(per, key=lambda k: per[k][0])
     d_ms, d_bytes = per[dom]
     achieved = d_bytes / (d_ms * 1e-3) / 1e9
-    kname = {"pack": "k_gather", "unpack": "k_gather", "backward": "k_segsum"}[dom]
-    traffic = read_traffic(f"{kname}_{dom}", args.workload)
+    kname = {"pack": "k_pack", "unpack": "k_unpack", "backward": "k_segsum"}[dom]
+    traffic = read_traffic(kname, args.workload)
     cpu = cpu_baseline(S, args.cpu_seconds) if S["host"] else None
     out = {
         "metric": "effective HBM GB/s (fwd pack+unpack, bwd) and % of peak; batched vs plain",

@@ -79,6 +79,8 @@ struct SegSumJob {
 };
 
 enum JobKind { KIND_GATHER = 0, KIND_SEGSUM = 1 };
+// Which phase a gather table serves (selects the kernel symbol only).
+enum GatherTag { TAG_PACK = 0, TAG_REDIST = 1, TAG_UNPACK = 2, TAG_TRANSFER = 3 };
 
 struct Sched {
   int tile_rows = 0;
@@ -96,6 +98,7 @@ hx_sched to_public(const Sched& s);
 // stays valid as long as the table lives.
 struct LaunchTable {
   int kind = KIND_GATHER;
+  int tag = TAG_TRANSFER;
   int dtype = HX_F64;
   int row_bytes = 0;
   int vec_bytes = 0;  // 16, 8 or 4: divides row_bytes and all base pointers
@@ -109,7 +112,7 @@ struct LaunchTable {
 };
 
 int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_bytes,
-                       const Sched& s, LaunchTable* t);
+                       const Sched& s, LaunchTable* t, int tag = TAG_TRANSFER);
 int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes,
                        const Sched& s, LaunchTable* t);
 int launch_table(const LaunchTable& t, hipStream_t stream);

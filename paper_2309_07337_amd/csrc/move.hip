@@ -75,9 +75,8 @@ __device__ __forceinline__ int find_job(const int64_t* __restrict__ ts, int njob
 // LPR lanes per row, U rows per lane in flight.
 // ---------------------------------------------------------------------------
 template <int VB, int NV, int LPR, int U, bool NT>
-__global__ void __launch_bounds__(512)
-k_gather(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs,
-         int64_t ntiles, int tile_rows, int nv_rt) {
+__device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
+                                            int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
   using V = typename RawVec<VB>::type;
   const int nv = NV > 0 ? NV : nv_rt;
   constexpr int NVPL = NV > 0 ? (NV + LPR - 1) / LPR : 1;
@@ -141,6 +140,22 @@ k_gather(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int
   }
 }
 
+// One kernel symbol per phase (same body), so profiles attribute time to the
+// pack (Start), the redistribution pack and the unpack (Wait), and the
+// simulated transfer separately.
+#define HX_GATHER_KERNEL(NAME)                                                                       \
+  template <int VB, int NV, int LPR, int U, bool NT>                                                 \
+  __global__ void __launch_bounds__(512)                                                             \
+      NAME(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs,            \
+           int64_t ntiles, int tile_rows, int nv_rt) {                                               \
+    gather_body<VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt);                      \
+  }
+HX_GATHER_KERNEL(k_pack)
+HX_GATHER_KERNEL(k_redist)
+HX_GATHER_KERNEL(k_unpack)
+HX_GATHER_KERNEL(k_transfer)
+#undef HX_GATHER_KERNEL
+
 // ---------------------------------------------------------------------------
 // Fixed-order segmented sum: out[i] = in[idx[ptr[i]]] + in[idx[ptr[i]+1]] + ...
 // Additions in T, strictly in ascending e, the accumulator starting from the
@@ -175,10 +190,19 @@ k_segsum(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts, int
       V* dp = reinterpret_cast<V*>(out + r * rb);
       for (int vi = lane_v; vi < nv; vi += LPR) {
         V acc = (V)(T)0;
-        if (p0 < p1) {
-          acc = reinterpret_cast<const V*>(in + (int64_t)ldv<int32_t, NT>(idx + p0) * rb)[vi];
-          for (int32_t e = p0 + 1; e < p1; ++e)
-            acc = acc + reinterpret_cast<const V*>(in + (int64_t)ldv<int32_t, NT>(idx + e) * rb)[vi];
+        // Terms are loaded K at a time (independent loads in flight) and then
+        // added strictly in ascending e: the order of additions is fixed.
+        constexpr int K = 4;
+        for (int32_t e0 = p0; e0 < p1; e0 += K) {
+          V v[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k)
+            if (e0 + k < p1)
+              v[k] = reinterpret_cast<const V*>(in + (int64_t)ldv<int32_t, NT>(idx + e0 + k) * rb)[vi];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            if (e0 + k < p1) acc = (e0 + k == p0) ? v[k] : acc + v[k];
+          }
         }
         stv<V, NT>(dp + vi, acc);
       }
@@ -189,15 +213,34 @@ k_segsum(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts, int
 // ---------------------------------------------------------------------------
 // Host-side dispatch.
 // ---------------------------------------------------------------------------
+template <int VB, int NV, int LPR, int U, bool NT>
+void go_gather_nt(const LaunchTable& t, hipStream_t s, int nv) {
+  const dim3 g(t.grid), b(t.sched.block_threads);
+  const GatherJob* jobs = t.jobs.as<GatherJob>();
+  const int64_t* ts = t.tile_start.as<int64_t>();
+  switch (t.tag) {
+    case TAG_PACK:
+      hipLaunchKernelGGL((k_pack<VB, NV, LPR, U, NT>), g, b, 0, s, jobs, ts, t.njobs, t.ntiles, t.sched.tile_rows, nv);
+      break;
+    case TAG_REDIST:
+      hipLaunchKernelGGL((k_redist<VB, NV, LPR, U, NT>), g, b, 0, s, jobs, ts, t.njobs, t.ntiles, t.sched.tile_rows,
+                         nv);
+      break;
+    case TAG_UNPACK:
+      hipLaunchKernelGGL((k_unpack<VB, NV, LPR, U, NT>), g, b, 0, s, jobs, ts, t.njobs, t.ntiles, t.sched.tile_rows,
+                         nv);
+      break;
+    default:
+      hipLaunchKernelGGL((k_transfer<VB, NV, LPR, U, NT>), g, b, 0, s, jobs, ts, t.njobs, t.ntiles,
+                         t.sched.tile_rows, nv);
+      break;
+  }
+}
+
 template <int VB, int NV, int LPR, int U>
 void go_gather(const LaunchTable& t, hipStream_t s, int nv) {
-  const dim3 g(t.grid), b(t.sched.block_threads);
-  if (t.sched.nontemporal)
-    hipLaunchKernelGGL((k_gather<VB, NV, LPR, U, true>), g, b, 0, s, t.jobs.as<GatherJob>(),
-                       t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows, nv);
-  else
-    hipLaunchKernelGGL((k_gather<VB, NV, LPR, U, false>), g, b, 0, s, t.jobs.as<GatherJob>(),
-                       t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows, nv);
+  if (t.sched.nontemporal) go_gather_nt<VB, NV, LPR, U, true>(t, s, nv);
+  else go_gather_nt<VB, NV, LPR, U, false>(t, s, nv);
 }
 
 template <class T, int VB, int NV, int LPR>
@@ -311,7 +354,8 @@ int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
 }  // namespace
 
 int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_bytes,
-                       const Sched& s, LaunchTable* t) {
+                       const Sched& s, LaunchTable* t, int tag) {
+  t->tag = tag;
   uintptr_t a = (uintptr_t)row_bytes;
   for (const auto& j : jobs) {
     if (j.nrows <= 0) continue;

@@ -190,7 +190,7 @@ static int build_req_tables(hx_req* r) {
     if (ph == PH_BWD) {
       if (!s.empty()) HX_TRY(build_segsum_table(s, r->dtype, (int)r->row_bytes, sc, &r->lt[ph]));
     } else {
-      HX_TRY(build_gather_table(g, r->dtype, (int)r->row_bytes, sc, &r->lt[ph]));
+      HX_TRY(build_gather_table(g, r->dtype, (int)r->row_bytes, sc, &r->lt[ph], ph));
     }
   }
   r->tables_built = true;
@@ -485,7 +485,7 @@ int hx::batch_build_table(const hx_batch* b, int phase, const Sched& sc, LaunchT
   }
   std::vector<GatherJob> all;
   for (auto& v : g) all.insert(all.end(), v.begin(), v.end());
-  return build_gather_table(all, b->dtype, (int)b->row_bytes, sc, t);
+  return build_gather_table(all, b->dtype, (int)b->row_bytes, sc, t, phase);
 }
 
 int hx::batch_build_plain(hx_batch* b, int phase) {
@@ -499,7 +499,7 @@ int hx::batch_build_plain(hx_batch* b, int phase) {
   b->plain[phase].resize(nm);
   for (size_t m = 0; m < nm; ++m) {
     if (phase == PH_BWD) HX_TRY(build_segsum_table(s[m], b->dtype, (int)b->row_bytes, sc, &b->plain[phase][m]));
-    else HX_TRY(build_gather_table(g[m], b->dtype, (int)b->row_bytes, sc, &b->plain[phase][m]));
+    else HX_TRY(build_gather_table(g[m], b->dtype, (int)b->row_bytes, sc, &b->plain[phase][m], phase));
   }
   b->plain_built[phase] = true;
   return HX_SUCCESS;
