@@ -28,7 +28,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2309_07337_amd", "csrc", "move.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2309_07337_amd", "csrc", f)
+               for f in ("move_kernels.h", "move_launch.h", "move_gather.hip", "move_scatter.hip",
+                         "move_segsum.hip", "move.hip")]
 
 
 def log(*a):
@@ -36,8 +38,13 @@ def log(*a):
 
 
 def kernel_src_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the data-movement kernel sources (a PMC summary is only valid
+    for the kernels it was taken on)."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(kernel: str, workload: str):
@@ -225,31 +232,36 @@ def time_steps(torch, P, batch, steps, warmup, plain, phases):
 
 
 def cpu_baseline(setup, budget_s):
-    """The oracle as it stands (numpy, one thread) on a bounded sample."""
+    """The oracle as it stands (numpy, one thread) on the same plans and the
+    same byte accounting: pack, identity unpack and fixed-order backward per
+    plan (the transpose of the pack map is init work, built untimed), passes
+    over the host-resident plans repeated until about budget_s of CPU time."""
     import numpy as np
     from oracle import move as OM
     from oracle import plan as OP
-    done_bytes, t = 0, 0.0
-    nplans = 0
+    plans = []
     for hk in setup["host"]:
         h, C = hk["x"].shape
-        rb = C * 8
         E = hk["idx"].size
-        U = np.unique(hk["idx"]).size
-        g = hk["x"]  # any [E, C] gradient of the same shape works for timing
-        t0 = time.perf_counter()
-        OM.pack(hk["x"], hk["idx"])
-        OM.gather_rows(hk["recv"], np.arange(h, dtype=np.int32))
         ptr, perm = OP.transpose_csr(hk["idx"], h)
-        OM.pack_transpose(g[:E], ptr, perm)
-        t += time.perf_counter() - t0
-        done_bytes += (E + U) * rb + 4 * E + 2 * h * rb + (E + h) * rb + 4 * (E + h + 1)
-        nplans += 1
-        if t > budget_s:
-            break
+        plans.append((hk, ptr, perm, np.arange(h, dtype=np.int32), np.unique(hk["idx"]).size, E, h, C * 8))
+    done_bytes, t, passes, nplans = 0, 0.0, 0, 0
+    while t < budget_s and plans:
+        for hk, ptr, perm, ident, U, E, h, rb in plans:
+            t0 = time.perf_counter()
+            OM.pack(hk["x"], hk["idx"])
+            OM.gather_rows(hk["recv"], ident)
+            OM.pack_transpose(hk["x"][:E], ptr, perm)   # any [E, C] gradient of this shape
+            t += time.perf_counter() - t0
+            done_bytes += (E + U) * rb + 4 * E + 2 * h * rb + (E + h) * rb + 4 * (E + h + 1)
+            nplans += 1
+            if t >= budget_s:
+                break
+        passes += 1
     return {"value": round(done_bytes / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nplans} of 256 plans ({done_bytes / 1e9:.2f} GB algorithmic, {t:.1f}s): "
-                      "numpy pack (np.take), identity unpack, fixed-order transpose sum"}
+            "sample": f"{nplans} plan steps over the first {len(plans)} of 256 plans ({passes} pass(es), "
+                      f"{done_bytes / 1e9:.2f} GB algorithmic in {t:.1f} s): numpy pack (np.take), identity "
+                      "unpack, fixed-order transpose sum"}
 
 
 def main():
@@ -262,8 +274,8 @@ def main():
     ap.add_argument("--plans", type=int, default=256)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-plans", type=int, default=40)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-plans", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: one rank's share (or a batch of "

@@ -77,6 +77,11 @@ typedef struct {
   int blocks_per_cu;  /* persistent grid = blocks_per_cu * #CUs */
   int nontemporal;    /* 1: streaming (non-temporal) loads/stores of index and output */
   int per_neighbor;   /* see above */
+  int unroll;         /* rows per lane in flight: 1, 2 or 4 (0 = default) */
+  int push_pack;      /* pack phase only: 1 = push form (walk the transpose of
+                         the pack map, read each source row once and write it
+                         to all its slots); 2 = pull form (gather per slot);
+                         0 = default (pull) */
 } hx_sched;
 
 /* ---------------------------------------------------------------------------

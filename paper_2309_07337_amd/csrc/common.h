@@ -78,7 +78,10 @@ struct SegSumJob {
   int64_t nrows;
 };
 
-enum JobKind { KIND_GATHER = 0, KIND_SEGSUM = 1 };
+// Gather: pull rows through an index (GatherJob).  Segsum: fixed-order sum
+// over the segments of a CSR (SegSumJob).  Scatter: push each row of a CSR's
+// rows to its slots (SegSumJob: in = rows, out = slots).
+enum JobKind { KIND_GATHER = 0, KIND_SEGSUM = 1, KIND_SCATTER = 2 };
 // Which phase a gather table serves (selects the kernel symbol only).
 enum GatherTag { TAG_PACK = 0, TAG_REDIST = 1, TAG_UNPACK = 2, TAG_TRANSFER = 3 };
 
@@ -88,6 +91,8 @@ struct Sched {
   int blocks_per_cu = 0;
   int nontemporal = 0;
   int per_neighbor = 0;
+  int unroll = 0;     // rows per lane in flight: 2, 4, 8 (0 = 4)
+  int push_pack = 0;  // pack in push form (read each source row once)
 };
 Sched default_sched(int kind, int row_bytes);
 Sched resolve_sched(const hx_sched* s, int kind, int row_bytes);
@@ -115,6 +120,8 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
                        const Sched& s, LaunchTable* t, int tag = TAG_TRANSFER);
 int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes,
                        const Sched& s, LaunchTable* t);
+int build_scatter_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes,
+                        const Sched& s, LaunchTable* t);
 int launch_table(const LaunchTable& t, hipStream_t stream);
 
 // Split a gather job per message (per neighbor) using the message counts.

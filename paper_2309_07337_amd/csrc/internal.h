@@ -83,15 +83,18 @@ struct hx_batch {
   hx::DevMem send_all, recv_all;             // [S1 | S2], [RECV1 | RECV2] of all ranks
   hx::DevMem gidx_pack, gidx_redist, gidx_unpack, gidx_x1, gidx_x2;
   hx::DevMem wb_ptr, wb_idx;                 // adjoint CSR: global column -> halo_all rows
+  hx::DevMem wp_ptr, wp_idx;                 // transpose of the pack map: global row -> send_all rows
   ~hx_batch();
 };
 
 namespace hx {
-int req_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<GatherJob>* g,
+int req_jobs(const hx_req* r, int phase, const Sched& sc, std::vector<GatherJob>* g,
              std::vector<SegSumJob>* s);
+int build_phase_table(int phase, const Sched& sc, int dtype, int row_bytes, const std::vector<GatherJob>& g,
+                      const std::vector<SegSumJob>& s, LaunchTable* t);
 void req_compute_bytes(hx_req* r);
 void batch_destroy_graphs(hx_batch* b);
-int batch_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged,
+int batch_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
                      std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s);
 int batch_build_table(const hx_batch* b, int phase, const Sched& sc, LaunchTable* t);
 int batch_build_plain(hx_batch* b, int phase);
@@ -99,7 +102,7 @@ int batch_prepare(hx_batch* b);
 int batch_run_start(hx_batch* b, hipStream_t s);
 int batch_run_wait(hx_batch* b, hipStream_t s);
 int batch_init_scheds(hx_batch* b, const hx_sched* sched);
-int world_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged,
+int world_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
                      std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s);
 
 // Device helpers implemented in plan.hip.

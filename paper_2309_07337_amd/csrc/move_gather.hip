@@ -1,0 +1,72 @@
+// Pull-form row gathers: pack (Start), redistribution pack and unpack (Wait),
+// and the simulated transfer.  One kernel symbol per phase (same body), so
+// profiles attribute time to each phase separately.
+#include "move_launch.h"
+
+namespace hx {
+namespace kern {
+namespace {
+
+#define HX_GATHER_KERNEL(NAME)                                                                 \
+  template <int VB, int NV, int LPR, int U, bool NT>                                           \
+  __global__ void __launch_bounds__(512)                                                       \
+      NAME(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs,      \
+           int64_t ntiles, int tile_rows, int nv_rt) {                                         \
+    gather_body<VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt);                \
+  }                                                                                            \
+  struct NAME##_go {                                                                           \
+    template <int VB, int NV, int LPR, int U, bool NT>                                         \
+    static void go(const LaunchTable& t, hipStream_t s, int nv) {                              \
+      hipLaunchKernelGGL((NAME<VB, NV, LPR, U, NT>), dim3(t.grid), dim3(t.sched.block_threads), \
+                         0, s, t.jobs.as<GatherJob>(), t.tile_start.as<int64_t>(), t.njobs,    \
+                         t.ntiles, t.sched.tile_rows, nv);                                     \
+    }                                                                                          \
+  };
+HX_GATHER_KERNEL(k_pack)
+HX_GATHER_KERNEL(k_redist)
+HX_GATHER_KERNEL(k_unpack)
+HX_GATHER_KERNEL(k_transfer)
+#undef HX_GATHER_KERNEL
+
+// The simulated transfer is not tuned: one fixed variant per shape.
+struct transfer_fixed {
+  template <int VB, int NV, int LPR, int U, bool NT>
+  static void go(const LaunchTable& t, hipStream_t s, int nv) {
+    k_transfer_go::go<VB, NV, LPR, (NV > 0 ? 4 : 1), false>(t, s, nv);
+  }
+};
+
+template <int VB>
+void transfer_shape(const LaunchTable& t, hipStream_t s) {
+  const int nv = t.row_bytes / VB;
+  if constexpr (VB == 16) {
+    if (nv == 8) return transfer_fixed::go<16, 8, 8, 4, false>(t, s, nv);
+    if (nv == 16) return transfer_fixed::go<16, 16, 16, 4, false>(t, s, nv);
+    if (nv == 1) return transfer_fixed::go<16, 1, 1, 4, false>(t, s, nv);
+  } else if constexpr (VB == 8) {
+    if (nv == 1) return transfer_fixed::go<8, 1, 1, 4, false>(t, s, nv);
+  } else {
+    if (nv == 1) return transfer_fixed::go<4, 1, 1, 4, false>(t, s, nv);
+  }
+  if (nv >= 16) return transfer_fixed::go<VB, 0, 16, 1, false>(t, s, nv);
+  return transfer_fixed::go<VB, 0, 1, 1, false>(t, s, nv);
+}
+
+}  // namespace
+}  // namespace kern
+
+void launch_gather_kernels(const LaunchTable& t, hipStream_t s) {
+  using namespace kern;
+  switch (t.tag) {
+    case TAG_PACK: by_vec<k_pack_go>(t, s); break;
+    case TAG_REDIST: by_vec<k_redist_go>(t, s); break;
+    case TAG_UNPACK: by_vec<k_unpack_go>(t, s); break;
+    default:
+      if (t.vec_bytes == 16) transfer_shape<16>(t, s);
+      else if (t.vec_bytes == 8) transfer_shape<8>(t, s);
+      else transfer_shape<4>(t, s);
+      break;
+  }
+}
+
+}  // namespace hx

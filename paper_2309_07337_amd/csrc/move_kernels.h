@@ -1,0 +1,416 @@
+// Device bodies of the data-movement kernels (included by the move_*.hip
+// translation units, which instantiate and launch them).
+//
+// All kernels are persistent and multi-job: a launch walks a table of jobs
+// cut into tiles of `tile_rows` rows.  Workgroup b runs on XCD b % 8
+// (round-robin dispatch), so logical workgroup ids are regrouped per XCD and
+// each logical workgroup takes a contiguous range of tiles: consecutive tiles
+// -- and the rows they share -- stay in one XCD's L2, and each XCD streams a
+// contiguous stretch of memory.  Rows move as 16/8/4-byte vectors with LPR
+// lanes per row; U rows per lane are loaded before any is stored, to keep
+// enough bytes in flight for HBM.  Pure data movement (plus adds in the
+// segmented sum): no matrix cores are involved.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace hx {
+namespace kern {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <int VB> struct RawVec;
+template <> struct RawVec<16> { using type = u32x4; };
+template <> struct RawVec<8> { using type = u32x2; };
+template <> struct RawVec<4> { using type = unsigned int; };
+
+template <class T, int VB> struct NumVec;
+template <> struct NumVec<float, 16> { using type = f32x4; };
+template <> struct NumVec<float, 8> { using type = f32x2; };
+template <> struct NumVec<float, 4> { using type = float; };
+template <> struct NumVec<double, 16> { using type = f64x2; };
+template <> struct NumVec<double, 8> { using type = double; };
+
+template <class T, bool NT>
+__device__ __forceinline__ T ldv(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <class T, bool NT>
+__device__ __forceinline__ void stv(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Contiguous tile range of this workgroup; workgroups of one XCD get
+// neighbouring ranges.  gridDim.x is a multiple of 8.
+__device__ __forceinline__ void tile_range(int64_t ntiles, int64_t* t0, int64_t* t1) {
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int per = nb >> 3;
+  const int L = (b & 7) * per + (b >> 3);
+  *t0 = (int64_t)L * ntiles / nb;
+  *t1 = (int64_t)(L + 1) * ntiles / nb;
+}
+
+// Largest j with ts[j] <= t (jobs with no tiles are skipped).
+__device__ __forceinline__ int find_job(const int64_t* __restrict__ ts, int njobs, int64_t t) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ts[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Pull: dst[r] = src[idx ? idx[r] : r].  NV vectors of VB bytes per row
+// (NV = 0: runtime nv, then U must be 1), LPR lanes per row.
+// ---------------------------------------------------------------------------
+template <int VB, int NV, int LPR, int U, bool NT>
+__device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
+                                            int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
+  using V = typename RawVec<VB>::type;
+  const int nv = NV > 0 ? NV : nv_rt;
+  constexpr int NVPL = NV > 0 ? (NV + LPR - 1) / LPR : 1;
+  const int lane_v = threadIdx.x % LPR;
+  const int rsub = threadIdx.x / LPR;
+  const int rows_per_pass = blockDim.x / LPR;
+  int64_t t0, t1;
+  tile_range(ntiles, &t0, &t1);
+  if (t0 >= t1) return;
+  int j = find_job(ts, njobs, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= ts[j + 1]) ++j;
+    const char* __restrict__ src = jobs[j].src;
+    char* __restrict__ dst = jobs[j].dst;
+    const int32_t* __restrict__ idx = jobs[j].idx;
+    const int64_t nrows = jobs[j].nrows;
+    const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
+    const size_t rb = (size_t)nv * VB;
+    if constexpr (NV > 0 && VB == 16) {
+      if (idx == nullptr) {
+        // identity job: the tile is one contiguous byte range; copy it as a
+        // flat stream of 16-byte vectors, 8 in flight per lane
+        constexpr int UC = 8;
+        const V* __restrict__ sp = reinterpret_cast<const V*>(src + r0 * rb);
+        V* __restrict__ dp = reinterpret_cast<V*>(dst + r0 * rb);
+        const int64_t nvec = (r1 - r0) * NV;
+        for (int64_t i = threadIdx.x; i < nvec; i += (int64_t)blockDim.x * UC) {
+          V c[UC];
+#pragma unroll
+          for (int u = 0; u < UC; ++u) {
+            const int64_t k = i + (int64_t)u * blockDim.x;
+            if (k < nvec) c[u] = ldv<V, NT>(sp + k);
+          }
+#pragma unroll
+          for (int u = 0; u < UC; ++u) {
+            const int64_t k = i + (int64_t)u * blockDim.x;
+            if (k < nvec) stv<V, NT>(dp + k, c[u]);
+          }
+        }
+        continue;
+      }
+    }
+    if constexpr (NV > 0) {
+      for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * U) {
+        V v[U][NVPL];
+        int64_t srow[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t r = base + (int64_t)u * rows_per_pass;
+          srow[u] = (r < r1) ? (idx ? (int64_t)ldv<int32_t, NT>(idx + r) : r) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (srow[u] >= 0) {
+            const V* sp = reinterpret_cast<const V*>(src + srow[u] * rb);
+#pragma unroll
+            for (int k = 0; k < NVPL; ++k) {
+              const int vi = lane_v + k * LPR;
+              if (NV % LPR == 0 || vi < NV) v[u][k] = idx ? sp[vi] : ldv<V, NT>(sp + vi);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t r = base + (int64_t)u * rows_per_pass;
+          if (srow[u] >= 0) {
+            V* dp = reinterpret_cast<V*>(dst + r * rb);
+#pragma unroll
+            for (int k = 0; k < NVPL; ++k) {
+              const int vi = lane_v + k * LPR;
+              if (NV % LPR == 0 || vi < NV) stv<V, NT>(dp + vi, v[u][k]);
+            }
+          }
+        }
+      }
+    } else {
+      for (int64_t r = r0 + rsub; r < r1; r += rows_per_pass) {
+        const int64_t s = idx ? (int64_t)ldv<int32_t, NT>(idx + r) : r;
+        const V* sp = reinterpret_cast<const V*>(src + s * rb);
+        V* dp = reinterpret_cast<V*>(dst + r * rb);
+        for (int vi = lane_v; vi < nv; vi += LPR) stv<V, NT>(dp + vi, sp[vi]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Push: for every source row r with slots idx[ptr[r] .. ptr[r+1]), read the
+// row once and write it to each of its slots (the transpose form of the
+// pull, so a row sent to several destinations is read from HBM once).
+// Job fields: in = source rows, out = destination slots.
+// ---------------------------------------------------------------------------
+constexpr int STAGE_ROWS = 512;     // tiles of at most this many rows stage their pointers
+constexpr int STAGE_ENTRIES = 2048;  // ... and their entry indices when they fit
+
+template <int VB, int NV, int LPR, int U, bool NT>
+__device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
+                                             int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
+  using V = typename RawVec<VB>::type;
+  const int nv = NV > 0 ? NV : nv_rt;
+  constexpr int NVPL = NV > 0 ? (NV + LPR - 1) / LPR : 1;
+  const int lane_v = threadIdx.x % LPR;
+  const int rsub = threadIdx.x / LPR;
+  const int rows_per_pass = blockDim.x / LPR;
+  __shared__ int32_t s_ptr[STAGE_ROWS + 1];
+  __shared__ int32_t s_idx[STAGE_ENTRIES];
+  const bool stage_ptr = NV > 0 && tile_rows <= STAGE_ROWS;
+  int64_t t0, t1;
+  tile_range(ntiles, &t0, &t1);
+  if (t0 >= t1) return;
+  int j = find_job(ts, njobs, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= ts[j + 1]) ++j;
+    const char* __restrict__ in = jobs[j].in;
+    char* __restrict__ out = jobs[j].out;
+    const int32_t* __restrict__ ptr = jobs[j].ptr;
+    const int32_t* __restrict__ idx = jobs[j].idx;
+    const int64_t nrows = jobs[j].nrows;
+    const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
+    const size_t rb = (size_t)nv * VB;
+    if constexpr (NV > 0) {
+      int32_t P0 = 0;
+      bool stage_idx = false;
+      if (stage_ptr) {
+        const int nt = (int)(r1 - r0);
+        for (int i = threadIdx.x; i <= nt; i += blockDim.x) s_ptr[i] = ptr[r0 + i];
+        __syncthreads();
+        P0 = s_ptr[0];
+        const int32_t ne = s_ptr[nt] - P0;
+        stage_idx = ne <= STAGE_ENTRIES;
+        if (stage_idx)
+          for (int i = threadIdx.x; i < ne; i += blockDim.x) s_idx[i] = ldv<int32_t, NT>(idx + P0 + i);
+        __syncthreads();
+      }
+      for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * U) {
+        int32_t a[U], len[U];
+        int maxlen = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t r = base + (int64_t)u * rows_per_pass;
+          a[u] = 0;
+          len[u] = 0;
+          if (r < r1) {
+            if (stage_ptr) {
+              a[u] = s_ptr[r - r0];
+              len[u] = s_ptr[r - r0 + 1] - a[u];
+            } else {
+              a[u] = ptr[r];
+              len[u] = ptr[r + 1] - a[u];
+            }
+          }
+          maxlen = max(maxlen, len[u]);
+        }
+        V v[U][NVPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (len[u] > 0) {
+            const V* sp = reinterpret_cast<const V*>(in + (base + (int64_t)u * rows_per_pass) * rb);
+#pragma unroll
+            for (int k = 0; k < NVPL; ++k) {
+              const int vi = lane_v + k * LPR;
+              if (NV % LPR == 0 || vi < NV) v[u][k] = ldv<V, NT>(sp + vi);
+            }
+          }
+        }
+        for (int d = 0; d < maxlen; ++d) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (d < len[u]) {
+              const int32_t e = a[u] + d;
+              const int32_t dst = stage_idx ? s_idx[e - P0] : ldv<int32_t, NT>(idx + e);
+              V* dp = reinterpret_cast<V*>(out + (int64_t)dst * rb);
+#pragma unroll
+              for (int k = 0; k < NVPL; ++k) {
+                const int vi = lane_v + k * LPR;
+                if (NV % LPR == 0 || vi < NV) stv<V, NT>(dp + vi, v[u][k]);
+              }
+            }
+          }
+        }
+      }
+      if (stage_ptr) __syncthreads();  // the next tile overwrites the staged indices
+    } else {
+      for (int64_t r = r0 + rsub; r < r1; r += rows_per_pass) {
+        const int32_t p0 = ptr[r], p1 = ptr[r + 1];
+        const V* sp = reinterpret_cast<const V*>(in + r * rb);
+        for (int vi = lane_v; vi < nv; vi += LPR) {
+          if (p0 >= p1) break;
+          const V v = sp[vi];
+          for (int32_t e = p0; e < p1; ++e)
+            stv<V, NT>(reinterpret_cast<V*>(out + (int64_t)idx[e] * rb) + vi, v);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order segmented sum: out[r] = in[idx[ptr[r]]] + in[idx[ptr[r]+1]] + ...
+// Additions in T, strictly in ascending position, the accumulator starting
+// from the first term (a lone -0 stays -0); an empty segment stores +0.
+// U rows per lane: the d-th terms of U rows are loaded together, then added
+// row by row, so the order of additions inside each row never changes.
+// ---------------------------------------------------------------------------
+// Index staging (here and in the push form above): the tile's row pointers
+// and, when they fit, its entry indices are loaded once into LDS with
+// coalesced loads, so each row then costs one dependent global access (its
+// terms) instead of three.
+
+template <class T, int VB, int NV, int LPR, int U, bool NT>
+__device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
+                                            int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
+  using V = typename NumVec<T, VB>::type;
+  const int nv = NV > 0 ? NV : nv_rt;
+  constexpr int NVPL = NV > 0 ? (NV + LPR - 1) / LPR : 1;
+  const int lane_v = threadIdx.x % LPR;
+  const int rsub = threadIdx.x / LPR;
+  const int rows_per_pass = blockDim.x / LPR;
+  __shared__ int32_t s_ptr[STAGE_ROWS + 1];
+  __shared__ int32_t s_idx[STAGE_ENTRIES];
+  const bool stage_ptr = NV > 0 && tile_rows <= STAGE_ROWS;
+  int64_t t0, t1;
+  tile_range(ntiles, &t0, &t1);
+  if (t0 >= t1) return;
+  int j = find_job(ts, njobs, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= ts[j + 1]) ++j;
+    const char* __restrict__ in = jobs[j].in;
+    char* __restrict__ out = jobs[j].out;
+    const int32_t* __restrict__ ptr = jobs[j].ptr;
+    const int32_t* __restrict__ idx = jobs[j].idx;
+    const int64_t nrows = jobs[j].nrows;
+    const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
+    const size_t rb = (size_t)nv * VB;
+    if constexpr (NV > 0) {
+      // prologue: stage the tile's pointers (and entries when they fit)
+      int32_t P0 = 0;
+      bool stage_idx = false;
+      if (stage_ptr) {
+        const int nt = (int)(r1 - r0);
+        for (int i = threadIdx.x; i <= nt; i += blockDim.x) s_ptr[i] = ptr[r0 + i];
+        __syncthreads();
+        P0 = s_ptr[0];
+        const int32_t ne = s_ptr[nt] - P0;
+        stage_idx = ne <= STAGE_ENTRIES;
+        if (stage_idx)
+          for (int i = threadIdx.x; i < ne; i += blockDim.x) s_idx[i] = ldv<int32_t, NT>(idx + P0 + i);
+        __syncthreads();
+      }
+      for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * U) {
+        int32_t a[U], len[U];
+        int maxlen = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t r = base + (int64_t)u * rows_per_pass;
+          a[u] = 0;
+          len[u] = -1;
+          if (r < r1) {
+            if (stage_ptr) {
+              a[u] = s_ptr[r - r0];
+              len[u] = s_ptr[r - r0 + 1] - a[u];
+            } else {
+              a[u] = ptr[r];
+              len[u] = ptr[r + 1] - a[u];
+            }
+          }
+          maxlen = max(maxlen, len[u]);
+        }
+        V acc[U][NVPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int k = 0; k < NVPL; ++k) acc[u][k] = (V)(T)0;
+        for (int d = 0; d < maxlen; ++d) {
+          V v[U][NVPL];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (d < len[u]) {
+              const int32_t e = a[u] + d;
+              const int32_t src = stage_idx ? s_idx[e - P0] : ldv<int32_t, NT>(idx + e);
+              const V* sp = reinterpret_cast<const V*>(in + (int64_t)src * rb);
+#pragma unroll
+              for (int k = 0; k < NVPL; ++k) {
+                const int vi = lane_v + k * LPR;
+                if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (d < len[u]) {
+#pragma unroll
+              for (int k = 0; k < NVPL; ++k) acc[u][k] = (d == 0) ? v[u][k] : acc[u][k] + v[u][k];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (len[u] >= 0) {
+            V* dp = reinterpret_cast<V*>(out + (base + (int64_t)u * rows_per_pass) * rb);
+#pragma unroll
+            for (int k = 0; k < NVPL; ++k) {
+              const int vi = lane_v + k * LPR;
+              if (NV % LPR == 0 || vi < NV) stv<V, NT>(dp + vi, acc[u][k]);
+            }
+          }
+        }
+      }
+      if (stage_ptr) __syncthreads();  // the next tile overwrites the staged indices
+    } else {
+      for (int64_t r = r0 + rsub; r < r1; r += rows_per_pass) {
+        const int32_t p0 = ptr[r];
+        const int32_t p1 = ptr[r + 1];
+        V* dp = reinterpret_cast<V*>(out + r * rb);
+        for (int vi = lane_v; vi < nv; vi += LPR) {
+          V acc = (V)(T)0;
+          for (int32_t e = p0; e < p1; ++e) {
+            const V v = reinterpret_cast<const V*>(in + (int64_t)ldv<int32_t, NT>(idx + e) * rb)[vi];
+            acc = (e == p0) ? v : acc + v;
+          }
+          stv<V, NT>(dp + vi, acc);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace kern
+
+// Launchers implemented in the move_*.hip translation units.
+void launch_gather_kernels(const LaunchTable& t, hipStream_t s);
+void launch_scatter_kernels(const LaunchTable& t, hipStream_t s);
+void launch_segsum_kernels(const LaunchTable& t, hipStream_t s);
+
+}  // namespace hx

@@ -96,6 +96,10 @@ Sched default_sched(int kind, int row_bytes) {
   rows = std::min(rows, 8192);
   if (kind == KIND_SEGSUM) rows = std::max(64, rows / 2);
   s.tile_rows = rows;
+  s.unroll = kind == KIND_SEGSUM ? 1 : 4;
+  // pull by default: on gfx950 scattered full-line writes cost more than the
+  // re-reads they save at fan-out ~1; the tuner tries push where fan-out is high
+  s.push_pack = 0;
   return s;
 }
 
@@ -107,6 +111,9 @@ Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
   if (p->blocks_per_cu > 0) s.blocks_per_cu = p->blocks_per_cu;
   s.nontemporal = p->nontemporal ? 1 : 0;
   s.per_neighbor = p->per_neighbor ? 1 : 0;
+  if (p->unroll > 0) s.unroll = p->unroll <= 1 ? 1 : (p->unroll == 2 ? 2 : 4);
+  if (p->push_pack == 1) s.push_pack = 1;
+  else if (p->push_pack == 2) s.push_pack = 0;
   return s;
 }
 
@@ -117,6 +124,8 @@ hx_sched to_public(const Sched& s) {
   o.blocks_per_cu = s.blocks_per_cu;
   o.nontemporal = s.nontemporal;
   o.per_neighbor = s.per_neighbor;
+  o.unroll = s.unroll;
+  o.push_pack = s.push_pack ? 1 : 2;
   return o;
 }
 
@@ -176,32 +185,45 @@ extern "C" int hx_topo_free(hx_topo** t) {
 // ===========================================================================
 // Requests
 // ===========================================================================
-static int req_phase_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<GatherJob>* g,
+static int req_phase_jobs(const hx_req* r, int phase, const Sched& sc, std::vector<GatherJob>* g,
                           std::vector<SegSumJob>* s);
+
+// Launch table of one phase from its jobs: the backward is a segmented sum;
+// the pack is a push (scatter) or a pull (gather) by the schedule; the other
+// phases are gathers.
+int hx::build_phase_table(int phase, const Sched& sc, int dtype, int row_bytes, const std::vector<GatherJob>& g,
+                          const std::vector<SegSumJob>& s, LaunchTable* t) {
+  if (phase == PH_BWD) return build_segsum_table(s, dtype, row_bytes, sc, t);
+  if (phase == PH_PACK && sc.push_pack) return build_scatter_table(s, dtype, row_bytes, sc, t);
+  return build_gather_table(g, dtype, row_bytes, sc, t, phase);
+}
 
 static int build_req_tables(hx_req* r) {
   if (r->tables_built) return HX_SUCCESS;
   for (int ph = 0; ph < 4; ++ph) {
     std::vector<GatherJob> g;
     std::vector<SegSumJob> s;
-    HX_TRY(req_phase_jobs(r, ph, false, &g, &s));
     const int kind = ph == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
     const Sched sc = default_sched(kind, (int)r->row_bytes);
-    if (ph == PH_BWD) {
-      if (!s.empty()) HX_TRY(build_segsum_table(s, r->dtype, (int)r->row_bytes, sc, &r->lt[ph]));
-    } else {
-      HX_TRY(build_gather_table(g, r->dtype, (int)r->row_bytes, sc, &r->lt[ph], ph));
-    }
+    HX_TRY(req_phase_jobs(r, ph, sc, &g, &s));
+    HX_TRY(build_phase_table(ph, sc, r->dtype, (int)r->row_bytes, g, s, &r->lt[ph]));
   }
   r->tables_built = true;
   return HX_SUCCESS;
 }
 
-static int req_phase_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<GatherJob>* g,
+static int req_phase_jobs(const hx_req* r, int phase, const Sched& sc, std::vector<GatherJob>* g,
                           std::vector<SegSumJob>* s) {
   const size_t rb = r->row_bytes;
+  const bool per_nbr = sc.per_neighbor != 0;
   switch (phase) {
     case PH_PACK: {
+      if (sc.push_pack) {
+        if (r->E1 > 0)
+          s->push_back(SegSumJob{r->x, r->send.as<char>(), r->bt_ptr.as<int32_t>(), r->bt_perm.as<int32_t>(),
+                                 r->n_local});
+        break;
+      }
       GatherJob j{r->x, r->send.as<char>(), r->s1_idx.as<int32_t>(), r->E1};
       if (per_nbr) split_gather_by_counts(j, r->s1_counts, rb, g);
       else g->push_back(j);
@@ -233,9 +255,9 @@ static int req_phase_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<
   return HX_SUCCESS;
 }
 
-int hx::req_jobs(const hx_req* r, int phase, bool per_nbr, std::vector<GatherJob>* g,
+int hx::req_jobs(const hx_req* r, int phase, const Sched& sc, std::vector<GatherJob>* g,
                  std::vector<SegSumJob>* s) {
-  return req_phase_jobs(r, phase, per_nbr, g, s);
+  return req_phase_jobs(r, phase, sc, g, s);
 }
 
 static int64_t count_distinct_host(const std::vector<int32_t>& idx, int64_t domain) {
@@ -377,9 +399,9 @@ extern "C" int hx_req_bind_grad(hx_req* r, const void* g_send, void* g_x) {
   r->lt[PH_BWD] = LaunchTable();
   std::vector<GatherJob> g;
   std::vector<SegSumJob> s;
-  HX_TRY(req_phase_jobs(r, PH_BWD, false, &g, &s));
-  HX_TRY(build_segsum_table(s, r->dtype, (int)r->row_bytes, default_sched(KIND_SEGSUM, (int)r->row_bytes),
-                            &r->lt[PH_BWD]));
+  const Sched sc = default_sched(KIND_SEGSUM, (int)r->row_bytes);
+  HX_TRY(req_phase_jobs(r, PH_BWD, sc, &g, &s));
+  HX_TRY(build_segsum_table(s, r->dtype, (int)r->row_bytes, sc, &r->lt[PH_BWD]));
   return HX_SUCCESS;
 }
 
@@ -457,15 +479,15 @@ hx_batch::~hx_batch() {
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
-int hx::batch_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged,
+int hx::batch_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
                          std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s) {
   g->clear();
   s->clear();
-  if (b->world) return world_phase_jobs(b, phase, per_nbr, merged, g, s);
+  if (b->world) return world_phase_jobs(b, phase, sc, merged, g, s);
   for (hx_req* r : b->members) {
     std::vector<GatherJob> gj;
     std::vector<SegSumJob> sj;
-    HX_TRY(req_phase_jobs(r, phase, per_nbr, &gj, &sj));
+    HX_TRY(req_phase_jobs(r, phase, sc, &gj, &sj));
     g->push_back(gj);
     s->push_back(sj);
   }
@@ -476,30 +498,30 @@ int hx::batch_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged
 int hx::batch_build_table(const hx_batch* b, int phase, const Sched& sc, LaunchTable* t) {
   std::vector<std::vector<GatherJob>> g;
   std::vector<std::vector<SegSumJob>> s;
-  HX_TRY(batch_phase_jobs(b, phase, sc.per_neighbor != 0, true, &g, &s));
+  HX_TRY(batch_phase_jobs(b, phase, sc, true, &g, &s));
   *t = LaunchTable();
-  if (phase == PH_BWD) {
-    std::vector<SegSumJob> all;
-    for (auto& v : s) all.insert(all.end(), v.begin(), v.end());
-    return build_segsum_table(all, b->dtype, (int)b->row_bytes, sc, t);
-  }
-  std::vector<GatherJob> all;
-  for (auto& v : g) all.insert(all.end(), v.begin(), v.end());
-  return build_gather_table(all, b->dtype, (int)b->row_bytes, sc, t, phase);
+  std::vector<GatherJob> ga;
+  std::vector<SegSumJob> sa;
+  for (auto& v : g) ga.insert(ga.end(), v.begin(), v.end());
+  for (auto& v : s) sa.insert(sa.end(), v.begin(), v.end());
+  return build_phase_table(phase, sc, b->dtype, (int)b->row_bytes, ga, sa, t);
 }
 
+// One launch per member: the plain form, with the library's default schedule.
 int hx::batch_build_plain(hx_batch* b, int phase) {
   b->plain[phase].clear();
   std::vector<std::vector<GatherJob>> g;
   std::vector<std::vector<SegSumJob>> s;
-  HX_TRY(batch_phase_jobs(b, phase, false, false, &g, &s));
   const int kind = phase == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
   const Sched sc = default_sched(kind, (int)b->row_bytes);
-  const size_t nm = phase == PH_BWD ? s.size() : g.size();
+  HX_TRY(batch_phase_jobs(b, phase, sc, false, &g, &s));
+  const size_t nm = std::max(g.size(), s.size());
   b->plain[phase].resize(nm);
   for (size_t m = 0; m < nm; ++m) {
-    if (phase == PH_BWD) HX_TRY(build_segsum_table(s[m], b->dtype, (int)b->row_bytes, sc, &b->plain[phase][m]));
-    else HX_TRY(build_gather_table(g[m], b->dtype, (int)b->row_bytes, sc, &b->plain[phase][m], phase));
+    static const std::vector<GatherJob> no_g;
+    static const std::vector<SegSumJob> no_s;
+    HX_TRY(build_phase_table(phase, sc, b->dtype, (int)b->row_bytes, m < g.size() ? g[m] : no_g,
+                             m < s.size() ? s[m] : no_s, &b->plain[phase][m]));
   }
   b->plain_built[phase] = true;
   return HX_SUCCESS;
@@ -543,7 +565,8 @@ static std::string cache_key(const hx_batch* b, int phase) {
   int njobs = 0;
   std::vector<std::vector<GatherJob>> g;
   std::vector<std::vector<SegSumJob>> s;
-  if (batch_phase_jobs(b, phase, false, true, &g, &s) == HX_SUCCESS) {
+  Sched neutral;  // the shape key counts rows of the pull form, whatever the schedule
+  if (batch_phase_jobs(b, phase, neutral, true, &g, &s) == HX_SUCCESS) {
     for (auto& v : g) for (auto& j : v) { rows += j.nrows; ++njobs; }
     for (auto& v : s) for (auto& j : v) { rows += j.nrows; ++njobs; }
   }
@@ -562,7 +585,8 @@ static bool cache_lookup(const std::string& key, Sched* out) {
   std::string k;
   Sched s;
   bool found = false;
-  while (f >> k >> s.tile_rows >> s.block_threads >> s.blocks_per_cu >> s.nontemporal >> s.per_neighbor) {
+  while (f >> k >> s.tile_rows >> s.block_threads >> s.blocks_per_cu >> s.nontemporal >> s.per_neighbor >> s.unroll >>
+         s.push_pack) {
     if (k == key) { *out = s; found = true; }
   }
   return found;
@@ -574,7 +598,7 @@ static void cache_store(const std::string& key, const Sched& s) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   std::ofstream f(path, std::ios::app);
   f << key << ' ' << s.tile_rows << ' ' << s.block_threads << ' ' << s.blocks_per_cu << ' ' << s.nontemporal
-    << ' ' << s.per_neighbor << '\n';
+    << ' ' << s.per_neighbor << ' ' << s.unroll << ' ' << s.push_pack << '\n';
 }
 
 int hx::batch_init_scheds(hx_batch* b, const hx_sched* sched) {
@@ -737,40 +761,55 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     if (b->lt[ph].empty()) continue;
     const int kind = ph == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
     const int rb = (int)b->row_bytes;
-    std::vector<Sched> cands;
     const int base = default_sched(kind, rb).tile_rows;
-    for (int tf : {1, 2, 4, 8, 16, 32})
-      for (int bpc : {2, 4, 8})
-        for (int bt : {256, 512})
-          for (int nt : {0, 1})
-            for (int pn : {0, 1}) {
-              if (pn && b->world) continue;
-              Sched c;
-              c.tile_rows = std::max(16, base * tf / 8);
-              c.block_threads = bt;
-              c.blocks_per_cu = bpc;
-              c.nontemporal = nt;
-              c.per_neighbor = pn;
-              cands.push_back(c);
-            }
     Sched best = b->sched[ph];
     float best_ms = 1e30f;
-    {
-      LaunchTable t;
-      rc = batch_build_table(b, ph, best, &t);
-      if (rc == HX_SUCCESS) rc = time_table(t, s, e0, e1, 3, &best_ms);
-    }
-    for (const Sched& c : cands) {
-      if (rc != HX_SUCCESS) break;
+    auto consider = [&](const Sched& c) {
+      if (rc != HX_SUCCESS) return;
       LaunchTable t;
       rc = batch_build_table(b, ph, c, &t);
-      if (rc != HX_SUCCESS) break;
+      if (rc != HX_SUCCESS) return;
       float ms = 0;
       rc = time_table(t, s, e0, e1, 3, &ms);
       if (rc == HX_SUCCESS && ms < best_ms * 0.98f) {
         best_ms = ms;
         best = c;
       }
+    };
+    consider(best);
+    // stage 1: work per tile, rows in flight, pull vs push (pack)
+    {
+      const Sched s0 = best;
+      for (int tf : {1, 2, 4, 8, 16, 32})
+        for (int u : {1, 2, 4})
+          for (int push : {0, 1}) {
+            if (push && ph != PH_PACK) continue;
+            Sched c = s0;
+            c.tile_rows = std::max(16, base * tf / 8);
+            c.unroll = u;
+            c.push_pack = ph == PH_PACK ? push : s0.push_pack;
+            c.per_neighbor = 0;
+            consider(c);
+          }
+    }
+    // stage 2: launch shape and streaming hints
+    {
+      const Sched s1 = best;
+      for (int bpc : {2, 4, 8})
+        for (int bt : {256, 512})
+          for (int nt : {0, 1}) {
+            Sched c = s1;
+            c.blocks_per_cu = bpc;
+            c.block_threads = bt;
+            c.nontemporal = nt;
+            consider(c);
+          }
+    }
+    // stage 3: one job per message (member batches, pull forms)
+    if (!b->world && !(ph == PH_PACK && best.push_pack) && ph != PH_BWD) {
+      Sched c = best;
+      c.per_neighbor = 1;
+      consider(c);
     }
     if (rc == HX_SUCCESS) {
       b->sched[ph] = best;

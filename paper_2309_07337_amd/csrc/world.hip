@@ -55,6 +55,21 @@ __global__ void k_add_rank_base(const int32_t* __restrict__ in, int64_t n, const
   }
 }
 
+// Transpose of the pack map in world coordinates: global row -> rows of
+// send_all, from the per-rank transposes (local rows, local slots).
+__global__ void k_world_pack_ptr(const int32_t* __restrict__ bt_ptr, const int64_t* __restrict__ bt_off,
+                                 const int64_t* __restrict__ rs, const int64_t* __restrict__ s1_off, int R, int64_t n,
+                                 int64_t E1_tot, int32_t* out) {
+  GRID_STRIDE(g, n + 1) {
+    if (g == n) {
+      out[g] = (int32_t)E1_tot;
+      continue;
+    }
+    const int q = upper_rank(rs, R, g);
+    out[g] = (int32_t)(bt_ptr[bt_off[q] + (g - rs[q])] + s1_off[q]);
+  }
+}
+
 // Unpack map in world coordinates: slot u of rank r's [stage-1 | stage-2]
 // receive arena -> row of recv_all.
 __global__ void k_world_unpack(const int32_t* __restrict__ u, int64_t n, const int64_t* __restrict__ hoff, int R,
@@ -108,15 +123,25 @@ int check_err(const DevMem& err, const char* what) {
 
 }  // namespace
 
-int world_phase_jobs(const hx_batch* b, int phase, bool per_nbr, bool merged,
+int world_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
                      std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s) {
-  (void)per_nbr;
   const int64_t rb = (int64_t)b->row_bytes;
   const char* sa = b->send_all.as<char>();
   const char* ra = b->recv_all.as<char>();
   switch (phase) {
     case PH_PACK:
-      if (merged) {
+      if (sc.push_pack) {
+        if (b->E1_tot == 0) break;
+        if (merged) {
+          s->push_back({SegSumJob{b->x_global, (char*)sa, b->wp_ptr.as<int32_t>(), b->wp_idx.as<int32_t>(), b->n}});
+        } else {
+          for (int r = 0; r < b->R; ++r) {
+            const int64_t r0 = b->row_starts[r];
+            s->push_back({SegSumJob{b->x_global + r0 * rb, (char*)sa, b->wp_ptr.as<int32_t>() + r0,
+                                    b->wp_idx.as<int32_t>(), b->row_starts[r + 1] - r0}});
+          }
+        }
+      } else if (merged) {
         g->push_back({GatherJob{b->x_global, (char*)sa, b->gidx_pack.as<int32_t>(), b->E1_tot}});
       } else {
         for (int r = 0; r < b->R; ++r)
@@ -320,6 +345,22 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
   if (b->E1_tot)
     hipLaunchKernelGGL(k_add_rank_base, dim3(blocks_for(b->E1_tot)), dim3(TB), 0, s, p->d[HX_F_S1_IDX].as<int32_t>(),
                        b->E1_tot, s1o.as<int64_t>(), R, rs_d.as<int64_t>(), b->gidx_pack.as<int32_t>());
+  // push form of the pack: global row -> send_all rows (ascending)
+  {
+    DevMem bto;
+    HX_TRY(upload_vec(bto, p->off[HX_F_BT_PTR]));
+    HX_TRY(b->wp_ptr.alloc((size_t)(b->n + 1) * 4));
+    HX_TRY(b->wp_idx.alloc((size_t)b->E1_tot * 4));
+    hipLaunchKernelGGL(k_world_pack_ptr, dim3(blocks_for(b->n + 1)), dim3(TB), 0, s, p->d[HX_F_BT_PTR].as<int32_t>(),
+                       bto.as<int64_t>(), rs_d.as<int64_t>(), s1o.as<int64_t>(), R, b->n, b->E1_tot,
+                       b->wp_ptr.as<int32_t>());
+    if (b->E1_tot)
+      hipLaunchKernelGGL(k_add_rank_base, dim3(blocks_for(b->E1_tot)), dim3(TB), 0, s,
+                         p->d[HX_F_BT_PERM].as<int32_t>(), b->E1_tot, s1o.as<int64_t>(), R, s1o.as<int64_t>(),
+                         b->wp_idx.as<int32_t>());
+    HX_HIP(hipGetLastError());
+    HX_HIP(hipDeviceSynchronize());
+  }
   // redistribution: rows of recv_all (stage-1 part of the forwarder)
   HX_TRY(b->gidx_redist.alloc((size_t)b->E2_tot * 4));
   if (b->E2_tot)
@@ -363,6 +404,8 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
   }
   // every index a kernel will follow stays inside its source
   HX_TRY(dev_check_range(b->gidx_pack.as<int32_t>(), b->E1_tot, b->n, "pack map", s));
+  HX_TRY(dev_check_range(b->wp_idx.as<int32_t>(), b->E1_tot, b->E1_tot, "pack transpose", s));
+  HX_TRY(dev_check_range(b->wp_ptr.as<int32_t>(), b->n + 1, b->E1_tot + 1, "pack transpose pointers", s));
   HX_TRY(dev_check_range(b->gidx_redist.as<int32_t>(), b->E2_tot, b->R1_tot, "redistribution map", s));
   if (!b->unpack_identity)
     HX_TRY(dev_check_range(b->gidx_unpack.as<int32_t>(), b->H_tot, b->R1_tot + b->R2_tot, "unpack map", s));

@@ -51,10 +51,12 @@ def reset(mem):
 
 
 SCHEDS = [None,
-          dict(tile_rows=64, block_threads=256, blocks_per_cu=1),
-          dict(tile_rows=1000, block_threads=512, blocks_per_cu=3, nontemporal=1),
-          dict(tile_rows=4096, block_threads=256, blocks_per_cu=8, per_neighbor=1),
-          dict(tile_rows=17, block_threads=512, blocks_per_cu=2, nontemporal=1, per_neighbor=1)]
+          dict(tile_rows=64, block_threads=256, blocks_per_cu=1, unroll=1, push_pack=1),
+          dict(tile_rows=1000, block_threads=512, blocks_per_cu=3, nontemporal=1, unroll=4, push_pack=2),
+          dict(tile_rows=4096, block_threads=256, blocks_per_cu=8, per_neighbor=1, push_pack=2),
+          dict(tile_rows=17, block_threads=512, blocks_per_cu=2, nontemporal=1, per_neighbor=1, unroll=4,
+               push_pack=1),
+          dict(tile_rows=333, block_threads=256, blocks_per_cu=4, nontemporal=1, unroll=4, push_pack=1)]
 
 
 @pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f32", 1), ("f64", 1), ("f32", 64)])

@@ -14,10 +14,10 @@ from workloads import random_small_csr, uniform_pm1
 pytestmark = pytest.mark.gpu
 
 
-def run_world(plan, x, H, plain_launch=False):
+def run_world(plan, x, H, plain_launch=False, sched=None):
     import torch
     halo = torch.full((H, x.shape[1]), float("nan"), dtype=x.dtype, device="cuda")
-    b = P.hx_batch_from_plan(plan, x, halo, flags=P.HX_WORLD_SIM_TRANSFER)
+    b = P.hx_batch_from_plan(plan, x, halo, flags=P.HX_WORLD_SIM_TRANSFER, sched=sched)
     if plain_launch:
         P.hx_batch_start_plain(b)
         P.hx_batch_wait_plain(b)
@@ -40,8 +40,10 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
     x = dev(xh)
     plan = gpu_plan(rs, rp, cols, ppn, variant)
     H = sum(h.size for h in halos)
-    for plain_launch in (False, True):
-        b, halo = run_world(plan, x, H, plain_launch)
+    variants = [(False, None), (True, None), (False, dict(push_pack=1, unroll=4, tile_rows=77)),
+                (False, dict(push_pack=2, unroll=2, nontemporal=1))]
+    for plain_launch, sched in variants:
+        b, halo = run_world(plan, x, H, plain_launch, sched)
         got = host(halo)
         ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
         assert bits_equal(got, ref)
