@@ -212,7 +212,7 @@ int hx_req_from_plan(const hx_plan* plan, int rank, const void* x_local, void* h
 int hx_start(hx_req* req, void* stream);
 int hx_wait(hx_req* req, void* stream);
 
-enum { HX_ARENA_SEND = 0, HX_ARENA_RECV = 1 };
+enum { HX_ARENA_SEND = 0, HX_ARENA_RECV = 1, HX_ARENA_GRAD_SEND = 4 };
 /* Device pointer and row count of a request's arena.  Send arena layout:
  * [stage-1 send (E1) | stage-2 send (E2)]; receive arena:
  * [stage-1 recv (R1) | stage-2 recv (R2)]; rows of ncols values. */
@@ -269,6 +269,12 @@ int hx_batch_tune(hx_batch* b, void* stream);
 int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out);
 /* World arenas: which = HX_ARENA_SEND / HX_ARENA_RECV, all ranks concatenated
  * as [stage-1 part of every rank | stage-2 part of every rank].
+ * which = HX_ARENA_GRAD_SEND (plain worlds, after hx_batch_bind_grad): the
+ * gradient slots of every rank's stage-1 send arena, laid out as the send
+ * arena's stage-1 part.  The world backward of a plain plan sums these slots;
+ * with HX_WORLD_SIM_TRANSFER the library fills them from g_halo_all (the
+ * reverse transfer), otherwise the caller's transport must fill them before
+ * hx_batch_backward.  Locality worlds read g_halo_all directly.
  * hx_batch_arena_offset gives the first row of a rank's stage-1 part
  * (which = HX_ARENA_SEND / HX_ARENA_RECV) or stage-2 part (which | 2);
  * rank = nranks gives the end of the part. */

@@ -63,7 +63,7 @@ struct hx_batch {
   hx::LaunchTable lt[4];
   std::vector<hx::LaunchTable> plain[4];
   bool plain_built[4] = {false, false, false, false};
-  hx::LaunchTable lt_xfer[2];
+  hx::LaunchTable lt_xfer[3];               // simulated transfers: stage 1, stage 2, reverse of stage 1
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   bool has_graph[3] = {false, false, false};
@@ -81,7 +81,8 @@ struct hx_batch {
   int64_t E1_tot = 0, E2_tot = 0, R1_tot = 0, R2_tot = 0, H_tot = 0;
   bool unpack_identity = true;
   hx::DevMem send_all, recv_all;             // [S1 | S2], [RECV1 | RECV2] of all ranks
-  hx::DevMem gidx_pack, gidx_redist, gidx_unpack, gidx_x1, gidx_x2;
+  hx::DevMem gidx_pack, gidx_redist, gidx_unpack, gidx_x1, gidx_x2, gidx_back;
+  hx::DevMem g_send_all;                     // plain worlds: gradients of every rank's send slots
   hx::DevMem wb_ptr, wb_idx;                 // adjoint CSR: global column -> halo_all rows
   hx::DevMem wp_ptr, wp_idx;                 // transpose of the pack map: global row -> send_all rows
   ~hx_batch();
@@ -101,6 +102,7 @@ int batch_build_plain(hx_batch* b, int phase);
 int batch_prepare(hx_batch* b);
 int batch_run_start(hx_batch* b, hipStream_t s);
 int batch_run_wait(hx_batch* b, hipStream_t s);
+int batch_run_backward(hx_batch* b, hipStream_t s);
 int batch_init_scheds(hx_batch* b, const hx_sched* sched);
 int world_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
                      std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s);

@@ -96,7 +96,7 @@ Sched default_sched(int kind, int row_bytes) {
   rows = std::min(rows, 8192);
   if (kind == KIND_SEGSUM) rows = std::max(64, rows / 2);
   s.tile_rows = rows;
-  s.unroll = kind == KIND_SEGSUM ? 1 : 4;
+  s.unroll = kind == KIND_SEGSUM ? 2 : 4;
   // pull by default: on gfx950 scattered full-line writes cost more than the
   // re-reads they save at fan-out ~1; the tuner tries push where fan-out is high
   s.push_pack = 0;
@@ -541,7 +541,7 @@ int hx::batch_prepare(hx_batch* b) {
                        &b->has_graph[0]));
   HX_TRY(capture_graph(b->cap_stream, [&](hipStream_t s) { return batch_run_wait(b, s); }, &b->graph[1],
                        &b->has_graph[1]));
-  HX_TRY(capture_graph(b->cap_stream, [&](hipStream_t s) { return launch_table(b->lt[PH_BWD], s); },
+  HX_TRY(capture_graph(b->cap_stream, [&](hipStream_t s) { return batch_run_backward(b, s); },
                        &b->graph[2], &b->has_graph[2]));
   return HX_SUCCESS;
 }
@@ -693,7 +693,24 @@ extern "C" int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out) {
   b->g_in = static_cast<const char*>(g_in);
   b->g_out = static_cast<char*>(g_out);
   b->plain_built[PH_BWD] = false;
+  if (b->unpack_identity) {
+    // plain world: halo gradients travel back to the senders' slots (the
+    // simulated reverse transfer), then each rank sums its own slots
+    HX_TRY(b->g_send_all.alloc((size_t)b->E1_tot * b->row_bytes));
+    std::vector<GatherJob> xb{GatherJob{b->g_in, b->g_send_all.as<char>(), b->gidx_back.as<int32_t>(), b->E1_tot}};
+    HX_TRY(build_gather_table(xb, b->dtype, (int)b->row_bytes, default_sched(KIND_GATHER, (int)b->row_bytes),
+                              &b->lt_xfer[2]));
+  }
   return batch_prepare(b);
+}
+
+// Backward of a batch: for plain worlds with the simulated transport, the
+// reverse transfer first; then the fixed-order sums.
+static int run_backward(hx_batch* b, hipStream_t s, bool plain_form) {
+  if (b->world && b->unpack_identity && (b->flags & HX_WORLD_SIM_TRANSFER)) HX_TRY(launch_table(b->lt_xfer[2], s));
+  if (!plain_form) return launch_table(b->lt[PH_BWD], s);
+  for (auto& t : b->plain[PH_BWD]) HX_TRY(launch_table(t, s));
+  return HX_SUCCESS;
 }
 
 extern "C" int hx_batch_backward(hx_batch* b, void* stream) {
@@ -715,9 +732,10 @@ extern "C" int hx_batch_backward(hx_batch* b, void* stream) {
 extern "C" int hx_batch_backward_plain(hx_batch* b, void* stream) {
   if (!b) return fail(HX_ERR_ARG, "null batch");
   if (!b->plain_built[PH_BWD]) HX_TRY(batch_build_plain(b, PH_BWD));
-  for (auto& t : b->plain[PH_BWD]) HX_TRY(launch_table(t, (hipStream_t)stream));
-  return HX_SUCCESS;
+  return run_backward(b, (hipStream_t)stream, true);
 }
+
+int hx::batch_run_backward(hx_batch* b, hipStream_t s) { return run_backward(b, s, false); }
 
 extern "C" int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out) {
   if (!b || !out || phase < 0 || phase > 3) return fail(HX_ERR_ARG, "bad argument");

@@ -70,6 +70,19 @@ __global__ void k_world_pack_ptr(const int32_t* __restrict__ bt_ptr, const int64
   }
 }
 
+__global__ void k_fill_neg(int32_t* p, int64_t n) {
+  GRID_STRIDE(i, n) p[i] = -1;
+}
+
+// inv[map[i]] = i for a permutation map (out-of-range targets are skipped and
+// leave -1, which the range check then reports).
+__global__ void k_invert(const int32_t* __restrict__ map, int64_t n, int32_t* inv) {
+  GRID_STRIDE(i, n) {
+    const int32_t t = map[i];
+    if (t >= 0 && t < n) inv[t] = (int32_t)i;
+  }
+}
+
 // Unpack map in world coordinates: slot u of rank r's [stage-1 | stage-2]
 // receive arena -> row of recv_all.
 __global__ void k_world_unpack(const int32_t* __restrict__ u, int64_t n, const int64_t* __restrict__ hoff, int R,
@@ -172,18 +185,25 @@ int world_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
         }
       }
       break;
-    case PH_BWD:
+    case PH_BWD: {
       if (!b->g_out) break;
+      // plain: each rank sums the gradients of its own send slots (the reverse
+      // transfer delivered them into g_send_all); other variants: the adjoint
+      // over halo_all rows directly
+      const bool local = b->unpack_identity;
+      const char* in = local ? b->g_send_all.as<char>() : b->g_in;
+      const int32_t* ptr = local ? b->wp_ptr.as<int32_t>() : b->wb_ptr.as<int32_t>();
+      const int32_t* idx = local ? b->wp_idx.as<int32_t>() : b->wb_idx.as<int32_t>();
       if (merged) {
-        s->push_back({SegSumJob{b->g_in, b->g_out, b->wb_ptr.as<int32_t>(), b->wb_idx.as<int32_t>(), b->n}});
+        s->push_back({SegSumJob{in, b->g_out, ptr, idx, b->n}});
       } else {
         for (int r = 0; r < b->R; ++r) {
           const int64_t r0 = b->row_starts[r];
-          s->push_back({SegSumJob{b->g_in, b->g_out + r0 * rb, b->wb_ptr.as<int32_t>() + r0, b->wb_idx.as<int32_t>(),
-                                  b->row_starts[r + 1] - r0}});
+          s->push_back({SegSumJob{in, b->g_out + r0 * rb, ptr + r0, idx, b->row_starts[r + 1] - r0}});
         }
       }
       break;
+    }
     default:
       return fail(HX_ERR_ARG, "bad phase");
   }
@@ -428,6 +448,17 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
     HX_TRY(build_gather_table(x1, dtype, (int)rb, sc, &b->lt_xfer[0]));
     HX_TRY(build_gather_table(x2, dtype, (int)rb, sc, &b->lt_xfer[1]));
   }
+  // plain worlds: the reverse of the stage-1 transfer (send slot -> the halo
+  // row that received it), used to deliver halo gradients back to the senders
+  if (b->unpack_identity && b->E1_tot > 0) {
+    if (b->E1_tot != b->R1_tot) return fail(HX_ERR_ARG, "plain plan: sends and receives differ in size");
+    HX_TRY(b->gidx_back.alloc((size_t)b->E1_tot * 4));
+    hipLaunchKernelGGL(k_fill_neg, dim3(blocks_for(b->E1_tot)), dim3(TB), 0, s, b->gidx_back.as<int32_t>(), b->E1_tot);
+    hipLaunchKernelGGL(k_invert, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, b->gidx_x1.as<int32_t>(), b->R1_tot,
+                       b->gidx_back.as<int32_t>());
+    HX_HIP(hipGetLastError());
+    HX_TRY(dev_check_range(b->gidx_back.as<int32_t>(), b->E1_tot, b->H_tot, "reverse transfer", s));
+  }
   // algorithmic bytes per phase
   {
     int64_t U1 = 0, U2 = 0;
@@ -454,6 +485,11 @@ extern "C" int hx_batch_arena(hx_batch* b, int which, void** dev_ptr, int64_t* r
   } else if (which == HX_ARENA_RECV) {
     *dev_ptr = b->recv_all.p;
     *rows = b->R1_tot + b->R2_tot;
+  } else if (which == HX_ARENA_GRAD_SEND) {
+    if (!b->unpack_identity) return fail(HX_ERR_ARG, "locality worlds have no gradient send arena");
+    if (!b->g_out) return fail(HX_ERR_STATE, "no gradient buffers bound");
+    *dev_ptr = b->g_send_all.p;
+    *rows = b->E1_tot;
   } else {
     return fail(HX_ERR_ARG, "bad arena id");
   }

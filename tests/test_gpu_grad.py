@@ -143,3 +143,44 @@ def test_finite_differences():
         fd = (losses[0] - losses[1]) / (float(vp) - float(vm))
         g = float(grad[r, c])
         assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (r, c, counts[r], fd, g)
+
+
+@pytest.mark.parametrize("sim", [True, False])
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+def test_world_backward_plain_launch_equals_graph(variant, sim):
+    """The one-launch-per-rank form of the world backward gives the same bits
+    as the captured graph, and both equal the oracle's adjoint.  Without the
+    simulated transport, a plain world's gradient send slots are filled by the
+    caller (here: copied from a simulated-transport world of the same plan)."""
+    need_gpu()
+    import torch
+    from paper_2309_07337_amd.autograd import HaloExchange
+    n, R, mx, pf, seed, uneven, ppn = case = CASES[3]
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    H = sum(h.size for h in halos)
+    C = 5
+    say(f"world backward plain vs graph {variant} sim={sim} case={case}")
+    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    g = dev(uniform_pm1_f32(seed + 17, H * C).reshape(H, C))
+    ref = HaloExchange(plan, n, H, C, dtype=torch.float32, sim_transfer=True)
+    ref.g_halo.copy_(g)
+    ref.backward()
+    ex = ref if sim else HaloExchange(plan, n, H, C, dtype=torch.float32, sim_transfer=False)
+    if not sim:
+        ex.g_halo.copy_(g)
+        if variant == "plain":
+            P.batch_arena_view(ex.batch, P.HX_ARENA_GRAD_SEND, C, torch.float32).copy_(
+                P.batch_arena_view(ref.batch, P.HX_ARENA_GRAD_SEND, C, torch.float32))
+        else:
+            with pytest.raises(P.HXError):
+                P.hx_batch_arena(ex.batch, P.HX_ARENA_GRAD_SEND)
+    P.hx_batch_backward(ex.batch)
+    torch.cuda.synchronize()
+    g_graph = host(ex.g_x).copy()
+    ex.g_x.fill_(float("nan"))
+    P.hx_batch_backward_plain(ex.batch)
+    torch.cuda.synchronize()
+    assert bits_equal(host(ex.g_x), g_graph)
+    gy = np.split(host(g), np.cumsum([h.size for h in halos])[:-1])
+    assert bits_equal(g_graph, OM.exchange_adjoint_reference(halos, gy, n))
