@@ -81,7 +81,8 @@ typedef struct {
   int push_pack;      /* pack phase only: 1 = push form (walk the transpose of
                          the pack map, read each source row once and write it
                          to all its slots); 2 = pull form (gather per slot);
-                         0 = default (pull) */
+                         0 = default (push for rows of 64 bytes or more,
+                         else pull) */
 } hx_sched;
 
 /* ---------------------------------------------------------------------------

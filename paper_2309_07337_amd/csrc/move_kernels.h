@@ -183,6 +183,7 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
   const int rows_per_pass = blockDim.x / LPR;
   __shared__ int32_t s_ptr[STAGE_ROWS + 1];
   __shared__ int32_t s_idx[STAGE_ENTRIES];
+  __shared__ int16_t s_row[STAGE_ENTRIES];
   const bool stage_ptr = NV > 0 && tile_rows <= STAGE_ROWS;
   int64_t t0, t1;
   tile_range(ntiles, &t0, &t1);
@@ -199,18 +200,58 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
     const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
     const size_t rb = (size_t)nv * VB;
     if constexpr (NV > 0) {
-      int32_t P0 = 0;
+      int32_t P0 = 0, ne = 0;
       bool stage_idx = false;
       if (stage_ptr) {
         const int nt = (int)(r1 - r0);
         for (int i = threadIdx.x; i <= nt; i += blockDim.x) s_ptr[i] = ptr[r0 + i];
         __syncthreads();
         P0 = s_ptr[0];
-        const int32_t ne = s_ptr[nt] - P0;
+        ne = s_ptr[nt] - P0;
         stage_idx = ne <= STAGE_ENTRIES;
-        if (stage_idx)
+        if (stage_idx) {
           for (int i = threadIdx.x; i < ne; i += blockDim.x) s_idx[i] = ldv<int32_t, NT>(idx + P0 + i);
+          // the tile row of every entry, so the entries can be spread over
+          // the lanes evenly whatever the rows' slot counts
+          for (int i = threadIdx.x; i < nt; i += blockDim.x)
+            for (int32_t e = s_ptr[i]; e < s_ptr[i + 1]; ++e) s_row[e - P0] = (int16_t)i;
+        }
         __syncthreads();
+      }
+      if (stage_idx) {
+        // entry-parallel: LPR lanes per entry, U entries per lane; entries of
+        // one row sit next to each other, so its reads coalesce or hit L2
+        for (int base = rsub; base < ne; base += rows_per_pass * U) {
+          V v[U][NVPL];
+          int32_t dsl[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = base + u * rows_per_pass;
+            dsl[u] = -1;
+            if (e < ne) {
+              dsl[u] = s_idx[e];
+              const V* sp = reinterpret_cast<const V*>(in + (r0 + s_row[e]) * (int64_t)rb);
+#pragma unroll
+              for (int k = 0; k < NVPL; ++k) {
+                const int vi = lane_v + k * LPR;
+                if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (dsl[u] >= 0) {
+              V* dp = reinterpret_cast<V*>(out + (int64_t)dsl[u] * rb);
+#pragma unroll
+              for (int k = 0; k < NVPL; ++k) {
+                const int vi = lane_v + k * LPR;
+                if (NV % LPR == 0 || vi < NV) stv<V, NT>(dp + vi, v[u][k]);
+              }
+            }
+          }
+        }
+        __syncthreads();  // the next tile overwrites the staged indices
+        continue;
       }
       for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * U) {
         int32_t a[U], len[U];
@@ -247,8 +288,7 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             if (d < len[u]) {
-              const int32_t e = a[u] + d;
-              const int32_t dst = stage_idx ? s_idx[e - P0] : ldv<int32_t, NT>(idx + e);
+              const int32_t dst = ldv<int32_t, NT>(idx + a[u] + d);
               V* dp = reinterpret_cast<V*>(out + (int64_t)dst * rb);
 #pragma unroll
               for (int k = 0; k < NVPL; ++k) {
@@ -259,7 +299,7 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
           }
         }
       }
-      if (stage_ptr) __syncthreads();  // the next tile overwrites the staged indices
+      if (stage_ptr) __syncthreads();  // the next tile overwrites the staged pointers
     } else {
       for (int64_t r = r0 + rsub; r < r1; r += rows_per_pass) {
         const int32_t p0 = ptr[r], p1 = ptr[r + 1];

@@ -97,9 +97,10 @@ Sched default_sched(int kind, int row_bytes) {
   if (kind == KIND_SEGSUM) rows = std::max(64, rows / 2);
   s.tile_rows = rows;
   s.unroll = kind == KIND_SEGSUM ? 2 : 4;
-  // pull by default: on gfx950 scattered full-line writes cost more than the
-  // re-reads they save at fan-out ~1; the tuner tries push where fan-out is high
-  s.push_pack = 0;
+  // rows of 64 B and more: push by default (on gfx950 scattered full-line
+  // writes run as fast as scattered reads, and the push form reads each
+  // source row once instead of once per slot); short rows: pull
+  s.push_pack = kind == KIND_GATHER && row_bytes >= 64 ? 1 : 0;
   return s;
 }
 

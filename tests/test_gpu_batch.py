@@ -56,7 +56,8 @@ SCHEDS = [None,
           dict(tile_rows=4096, block_threads=256, blocks_per_cu=8, per_neighbor=1, push_pack=2),
           dict(tile_rows=17, block_threads=512, blocks_per_cu=2, nontemporal=1, per_neighbor=1, unroll=4,
                push_pack=1),
-          dict(tile_rows=333, block_threads=256, blocks_per_cu=4, nontemporal=1, unroll=4, push_pack=1)]
+          dict(tile_rows=333, block_threads=256, blocks_per_cu=4, nontemporal=1, unroll=4, push_pack=1),
+          dict(tile_rows=2048, block_threads=256, blocks_per_cu=2, unroll=2, push_pack=1)]
 
 
 @pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f32", 1), ("f64", 1), ("f32", 64)])
@@ -129,3 +130,36 @@ def test_batch_state_machine():
     with pytest.raises(P.HXError) as e:
         P.hx_batch_init([mem[0]["req"], other])
     assert e.value.code == P.HX_ERR_ARG
+
+
+@pytest.mark.parametrize("sched", [dict(tile_rows=16, push_pack=1), dict(tile_rows=64, push_pack=1, unroll=2),
+                                   dict(tile_rows=4096, push_pack=1), dict(tile_rows=64, push_pack=2)])
+def test_high_fan_out(sched):
+    """Every source row goes to 100 neighbors: push tiles whose entries do not
+    fit the staging buffer (64 rows x 100 slots) take the row-parallel form,
+    smaller tiles the entry-parallel one; the backward sums 100 terms per row."""
+    need_gpu()
+    import torch
+    n, k, C = 90, 100, 16
+    say("high fan-out", sched)
+    x = dev(uniform_pm1(77, n * C).reshape(n, C))
+    idx = np.tile(np.arange(n, dtype=np.int32), k)
+    counts = np.full(k, n, np.int32)
+    displs = (np.arange(k) * n).astype(np.int32)
+    halo = torch.full((k, C), float("nan"), dtype=torch.float64, device="cuda")
+    procs = list(range(1, k + 1))
+    topo = P.hx_topo_create(0, k + 1, procs, procs)
+    req = P.hx_neighbor_alltoallv_init(x, counts, displs, idx, halo, np.ones(k, np.int32),
+                                       np.arange(k, dtype=np.int32), topo)
+    g_send = dev(uniform_pm1(78, n * k * C).reshape(n * k, C))
+    g_x = torch.full_like(x, float("nan"))
+    P.hx_req_bind_grad(req, g_send, g_x)
+    b = P.hx_batch_init([req], sched=sched)
+    P.hx_batch_start(b)
+    P.hx_batch_wait(b)
+    P.hx_batch_backward(b)
+    send = host(P.req_arena_view(req, P.HX_ARENA_SEND, C, torch.float64))
+    assert bits_equal(send, OM.pack(host(x), idx))
+    ptr, perm = OP.transpose_csr(idx, n)
+    assert bits_equal(host(g_x), OM.pack_transpose(host(g_send), ptr, perm))
+    b.free()
