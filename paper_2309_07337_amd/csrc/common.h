@@ -95,6 +95,14 @@ struct Sched {
   int push_pack = 0;  // pack in push form (read each source row once)
 };
 Sched default_sched(int kind, int row_bytes);
+
+// LDS staging in the CSR-driven kernels (push pack, segmented sum): tiles of
+// at most kStageRows rows stage their row pointers, and their entry indices
+// when there are at most kStageEntries; the segmented sum gathers the terms
+// of consecutive rows into kSegValueBytes of LDS before adding them.
+constexpr int kStageRows = 512;
+constexpr int kStageEntries = 2048;
+constexpr int kSegValueBytes = 32768;
 Sched resolve_sched(const hx_sched* s, int kind, int row_bytes);
 hx_sched to_public(const Sched& s);
 

@@ -167,10 +167,14 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
 // Push: for every source row r with slots idx[ptr[r] .. ptr[r+1]), read the
 // row once and write it to each of its slots (the transpose form of the
 // pull, so a row sent to several destinations is read from HBM once).
-// Job fields: in = source rows, out = destination slots.
+// Staged tiles run entry-parallel (LPR lanes per slot, U slots per lane);
+// other tiles row-parallel.  Job fields: in = source rows, out = slots.
 // ---------------------------------------------------------------------------
-constexpr int STAGE_ROWS = 512;     // tiles of at most this many rows stage their pointers
-constexpr int STAGE_ENTRIES = 2048;  // ... and their entry indices when they fit
+// LDS staging limits (kStageRows, kStageEntries, kSegValueBytes) are declared
+// with the schedules in common.h, where the default tile sizes use them.
+constexpr int STAGE_ROWS = kStageRows;
+constexpr int STAGE_ENTRIES = kStageEntries;
+constexpr int SEG_VALUE_BYTES = kSegValueBytes;
 
 template <int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
@@ -319,8 +323,10 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
 // Fixed-order segmented sum: out[r] = in[idx[ptr[r]]] + in[idx[ptr[r]+1]] + ...
 // Additions in T, strictly in ascending position, the accumulator starting
 // from the first term (a lone -0 stays -0); an empty segment stores +0.
-// U rows per lane: the d-th terms of U rows are loaded together, then added
-// row by row, so the order of additions inside each row never changes.
+// Staged tiles go chunk by chunk: the terms of a run of consecutive rows are
+// gathered into LDS entry-parallel (U terms per lane in flight, however the
+// segment lengths vary), then each row adds its own terms from LDS in order.
+// Other tiles run row-parallel, term by term.
 // ---------------------------------------------------------------------------
 // Index staging (here and in the push form above): the tile's row pointers
 // and, when they fit, its entry indices are loaded once into LDS with
@@ -338,6 +344,7 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
   const int rows_per_pass = blockDim.x / LPR;
   __shared__ int32_t s_ptr[STAGE_ROWS + 1];
   __shared__ int32_t s_idx[STAGE_ENTRIES];
+  __shared__ V s_val[NV > 0 ? SEG_VALUE_BYTES / VB : 1];
   const bool stage_ptr = NV > 0 && tile_rows <= STAGE_ROWS;
   int64_t t0, t1;
   tile_range(ntiles, &t0, &t1);
@@ -357,8 +364,8 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
       // prologue: stage the tile's pointers (and entries when they fit)
       int32_t P0 = 0;
       bool stage_idx = false;
+      const int nt = (int)(r1 - r0);
       if (stage_ptr) {
-        const int nt = (int)(r1 - r0);
         for (int i = threadIdx.x; i <= nt; i += blockDim.x) s_ptr[i] = ptr[r0 + i];
         __syncthreads();
         P0 = s_ptr[0];
@@ -368,11 +375,96 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
           for (int i = threadIdx.x; i < ne; i += blockDim.x) s_idx[i] = ldv<int32_t, NT>(idx + P0 + i);
         __syncthreads();
       }
-      for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * U) {
-        int32_t a[U], len[U];
+      if (stage_idx) {
+        // Chunks of consecutive rows whose terms fit in s_val: the terms are
+        // loaded entry-parallel (U per lane, all in flight together, whatever
+        // the segment lengths), then every row adds its own terms from LDS in
+        // entry order and stores the sum.
+        constexpr int CAP = SEG_VALUE_BYTES / (NV * VB);  // terms per chunk
+        int ra = 0;
+        while (ra < nt) {
+          int lo = ra, hi = nt;  // last row boundary whose terms still fit
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_ptr[mid] - s_ptr[ra] <= CAP) lo = mid; else hi = mid - 1;
+          }
+          if (lo == ra) {
+            // one row with more terms than fit: its first lane group sums it
+            // straight from global memory, in order
+            if (rsub == 0) {
+              const int32_t a = s_ptr[ra] - P0, len = s_ptr[ra + 1] - s_ptr[ra];
+              V* dp = reinterpret_cast<V*>(out + (r0 + ra) * (int64_t)rb);
+#pragma unroll
+              for (int k = 0; k < NVPL; ++k) {
+                const int vi = lane_v + k * LPR;
+                if (NV % LPR == 0 || vi < NV) {
+                  V acc = reinterpret_cast<const V*>(in + (int64_t)s_idx[a] * rb)[vi];
+                  for (int32_t d = 1; d < len; ++d)
+                    acc = acc + reinterpret_cast<const V*>(in + (int64_t)s_idx[a + d] * rb)[vi];
+                  stv<V, NT>(dp + vi, acc);
+                }
+              }
+            }
+            __syncthreads();
+            ++ra;
+            continue;
+          }
+          const int rq = lo;
+          const int ea = s_ptr[ra] - P0, eb = s_ptr[rq] - P0;
+          for (int base = ea + rsub; base < eb; base += rows_per_pass * U) {
+            V v[U][NVPL];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int e = base + u * rows_per_pass;
+              if (e < eb) {
+                const V* sp = reinterpret_cast<const V*>(in + (int64_t)s_idx[e] * rb);
+#pragma unroll
+                for (int k = 0; k < NVPL; ++k) {
+                  const int vi = lane_v + k * LPR;
+                  if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
+                }
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int e = base + u * rows_per_pass;
+              if (e < eb) {
+#pragma unroll
+                for (int k = 0; k < NVPL; ++k) {
+                  const int vi = lane_v + k * LPR;
+                  if (NV % LPR == 0 || vi < NV) s_val[(e - ea) * NV + vi] = v[u][k];
+                }
+              }
+            }
+          }
+          __syncthreads();
+          for (int r = ra + rsub; r < rq; r += rows_per_pass) {
+            const int a = s_ptr[r] - P0 - ea, len = s_ptr[r + 1] - s_ptr[r];
+            V* dp = reinterpret_cast<V*>(out + (r0 + r) * (int64_t)rb);
+#pragma unroll
+            for (int k = 0; k < NVPL; ++k) {
+              const int vi = lane_v + k * LPR;
+              if (NV % LPR == 0 || vi < NV) {
+                V acc = (V)(T)0;
+                if (len > 0) acc = s_val[a * NV + vi];
+                for (int d = 1; d < len; ++d) acc = acc + s_val[(a + d) * NV + vi];
+                stv<V, NT>(dp + vi, acc);
+              }
+            }
+          }
+          __syncthreads();  // s_val, s_ptr and s_idx are reused next
+          ra = rq;
+        }
+        continue;
+      }
+      // row-parallel fallback (tiles whose entries were not staged): one
+      // term of UR rows per lane in flight, the terms of a row in order
+      constexpr int UR = 1;
+      for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * UR) {
+        int32_t a[UR], len[UR];
         int maxlen = 0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UR; ++u) {
           const int64_t r = base + (int64_t)u * rows_per_pass;
           a[u] = 0;
           len[u] = -1;
@@ -387,15 +479,15 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
           }
           maxlen = max(maxlen, len[u]);
         }
-        V acc[U][NVPL];
+        V acc[UR][NVPL];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < UR; ++u)
 #pragma unroll
           for (int k = 0; k < NVPL; ++k) acc[u][k] = (V)(T)0;
         for (int d = 0; d < maxlen; ++d) {
-          V v[U][NVPL];
+          V v[UR][NVPL];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
+          for (int u = 0; u < UR; ++u) {
             if (d < len[u]) {
               const int32_t e = a[u] + d;
               const int32_t src = stage_idx ? s_idx[e - P0] : ldv<int32_t, NT>(idx + e);
@@ -408,7 +500,7 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
             }
           }
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
+          for (int u = 0; u < UR; ++u) {
             if (d < len[u]) {
 #pragma unroll
               for (int k = 0; k < NVPL; ++k) acc[u][k] = (d == 0) ? v[u][k] : acc[u][k] + v[u][k];
@@ -416,7 +508,7 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
           }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UR; ++u) {
           if (len[u] >= 0) {
             V* dp = reinterpret_cast<V*>(out + (base + (int64_t)u * rows_per_pass) * rb);
 #pragma unroll

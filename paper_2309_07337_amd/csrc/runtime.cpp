@@ -94,9 +94,11 @@ Sched default_sched(int kind, int row_bytes) {
   // about 32 KiB of output per tile
   int rows = std::max(64, (32 << 10) / std::max(row_bytes, 1));
   rows = std::min(rows, 8192);
-  if (kind == KIND_SEGSUM) rows = std::max(64, rows / 2);
+  // segmented sum: the largest tile whose row pointers are staged in LDS
+  if (kind == KIND_SEGSUM) rows = std::min(kStageRows, std::max(64, (64 << 10) / std::max(row_bytes, 1)));
   s.tile_rows = rows;
-  s.unroll = kind == KIND_SEGSUM ? 2 : 4;
+  s.unroll = 4;
+  if (kind == KIND_SEGSUM) s.block_threads = 512;
   // rows of 64 B and more: push by default (on gfx950 scattered full-line
   // writes run as fast as scattered reads, and the push form reads each
   // source row once instead of once per slot); short rows: pull
