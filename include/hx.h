@@ -83,6 +83,12 @@ typedef struct {
                          to all its slots); 2 = pull form (gather per slot);
                          0 = default (push for rows of 64 bytes or more,
                          else pull) */
+  int lds_window;     /* gathers: 1 = a job whose indices stay inside a known
+                         window of source rows (a rank's owned rows, its
+                         stage-1 receive arena) copies that window into LDS
+                         (when it fits in 80 KiB) and gathers from LDS;
+                         2 = gather from global memory; 0 = default (1 for
+                         rows of 16 bytes or less, else 2) */
 } hx_sched;
 
 /* ---------------------------------------------------------------------------

@@ -57,16 +57,21 @@ int upload_vec(DevMem& dst, const std::vector<T>& v) {
 }
 
 int device_cus();  // number of compute units of the current device
+int device_lds_per_block();  // LDS bytes one workgroup may use on the current device
 
 // ---------------------------------------------------------------------------
 // Kernels' work descriptions.
 // ---------------------------------------------------------------------------
 // dst[r, :] = src[idx ? idx[r] : r, :] for r < nrows (rows of row_bytes).
+// A job may name a source window: every idx[r] lies in [win_lo, win_lo +
+// win_rows) (win_rows = 0: no window), which lets the kernel stage it in LDS.
 struct GatherJob {
   const char* src;
   char* dst;
   const int32_t* idx;
   int64_t nrows;
+  int64_t win_lo = 0;
+  int64_t win_rows = 0;
 };
 // out[i, :] = in[idx[ptr[i]], :] + in[idx[ptr[i]+1], :] + ... (ascending,
 // first term first; empty -> +0) for i < nrows.
@@ -93,6 +98,7 @@ struct Sched {
   int per_neighbor = 0;
   int unroll = 0;     // rows per lane in flight: 2, 4, 8 (0 = 4)
   int push_pack = 0;  // pack in push form (read each source row once)
+  int lds_window = 0; // gathers stage each job's source window in LDS
 };
 Sched default_sched(int kind, int row_bytes);
 
@@ -103,6 +109,9 @@ Sched default_sched(int kind, int row_bytes);
 constexpr int kStageRows = 512;
 constexpr int kStageEntries = 2048;
 constexpr int kSegValueBytes = 32768;
+// Largest source window a gather stages in LDS (larger ones read global
+// memory): two such workgroups fit in the 160 KiB of a gfx950 CU.
+constexpr int kWinBytes = 80 << 10;
 Sched resolve_sched(const hx_sched* s, int kind, int row_bytes);
 hx_sched to_public(const Sched& s);
 
@@ -115,6 +124,7 @@ struct LaunchTable {
   int dtype = HX_F64;
   int row_bytes = 0;
   int vec_bytes = 0;  // 16, 8 or 4: divides row_bytes and all base pointers
+  int win_bytes = 0;  // dynamic LDS of a gather table whose jobs use windows
   Sched sched;
   int njobs = 0;
   int64_t ntiles = 0;

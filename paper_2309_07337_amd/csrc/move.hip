@@ -79,7 +79,24 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
     if (j.nrows <= 0) continue;
     a |= (uintptr_t)j.src | (uintptr_t)j.dst;
   }
-  return build_table(jobs, KIND_GATHER, dtype, row_bytes, s, t, a);
+  // source windows: kept where the schedule asks for them and they fit
+  std::vector<GatherJob> w(jobs);
+  int64_t win_bytes = 0;
+  const int64_t win_cap = std::min<int64_t>(kWinBytes, device_lds_per_block());
+  for (auto& j : w) {
+    const int64_t bytes = j.win_rows * (int64_t)row_bytes;
+    if (!s.lds_window || j.idx == nullptr || j.win_rows <= 0 || bytes > win_cap || j.win_lo < 0) {
+      j.win_lo = 0;
+      j.win_rows = 0;
+    } else {
+      a |= (uintptr_t)(j.src + j.win_lo * (int64_t)row_bytes);
+      win_bytes = std::max(win_bytes, bytes);
+    }
+  }
+  HX_TRY(build_table(w, KIND_GATHER, dtype, row_bytes, s, t, a));
+  // (the runtime-row-size kernel form ignores windows and reads global memory)
+  t->win_bytes = t->ntiles > 0 ? (int)win_bytes : 0;
+  return HX_SUCCESS;
 }
 
 int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,

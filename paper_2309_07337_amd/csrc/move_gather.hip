@@ -11,15 +11,16 @@ namespace {
   template <int VB, int NV, int LPR, int U, bool NT>                                           \
   __global__ void __launch_bounds__(512)                                                       \
       NAME(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs,      \
-           int64_t ntiles, int tile_rows, int nv_rt) {                                         \
-    gather_body<VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt);                \
+           int64_t ntiles, int tile_rows, int nv_rt, int use_win) {                            \
+    gather_body<VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt, use_win);       \
   }                                                                                            \
   struct NAME##_go {                                                                           \
     template <int VB, int NV, int LPR, int U, bool NT>                                         \
     static void go(const LaunchTable& t, hipStream_t s, int nv) {                              \
       hipLaunchKernelGGL((NAME<VB, NV, LPR, U, NT>), dim3(t.grid), dim3(t.sched.block_threads), \
-                         0, s, t.jobs.as<GatherJob>(), t.tile_start.as<int64_t>(), t.njobs,    \
-                         t.ntiles, t.sched.tile_rows, nv);                                     \
+                         (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                     \
+                         t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows, nv, \
+                         t.win_bytes > 0 ? 1 : 0);                                             \
     }                                                                                          \
   };
 HX_GATHER_KERNEL(k_pack)

@@ -73,19 +73,29 @@ __device__ __forceinline__ int find_job(const int64_t* __restrict__ ts, int njob
 // Pull: dst[r] = src[idx ? idx[r] : r].  NV vectors of VB bytes per row
 // (NV = 0: runtime nv, then U must be 1), LPR lanes per row.
 // ---------------------------------------------------------------------------
+// Source windows (use_win != 0, fixed shapes only): a job with win_rows > 0
+// reads only source rows [win_lo, win_lo + win_rows), and the table's
+// dynamic LDS holds that many rows.  The workgroup copies the window into
+// LDS with coalesced loads when it reaches a new such job and then gathers
+// from LDS: one wide read of the window instead of one L2 request per
+// (usually short, scattered) row.  Indices outside the window read global
+// memory.
 template <int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
-                                            int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
+                                            int njobs, int64_t ntiles, int tile_rows, int nv_rt, int use_win) {
   using V = typename RawVec<VB>::type;
   const int nv = NV > 0 ? NV : nv_rt;
   constexpr int NVPL = NV > 0 ? (NV + LPR - 1) / LPR : 1;
   const int lane_v = threadIdx.x % LPR;
   const int rsub = threadIdx.x / LPR;
   const int rows_per_pass = blockDim.x / LPR;
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  V* __restrict__ s_win = reinterpret_cast<V*>(s_dyn);
   int64_t t0, t1;
   tile_range(ntiles, &t0, &t1);
   if (t0 >= t1) return;
   int j = find_job(ts, njobs, t0);
+  int staged = -1;
   for (int64_t t = t0; t < t1; ++t) {
     while (t >= ts[j + 1]) ++j;
     const char* __restrict__ src = jobs[j].src;
@@ -95,6 +105,21 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
     const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
     const size_t rb = (size_t)nv * VB;
+    int64_t win_lo = 0, win_rows = 0;
+    if constexpr (NV > 0) {
+      if (use_win && idx != nullptr && jobs[j].win_rows > 0) {
+        win_lo = jobs[j].win_lo;
+        win_rows = jobs[j].win_rows;
+        if (staged != j) {
+          __syncthreads();  // every lane is done with the previous window
+          const V* __restrict__ wp = reinterpret_cast<const V*>(src + win_lo * (int64_t)rb);
+          const int nvec = (int)win_rows * NV;
+          for (int i = threadIdx.x; i < nvec; i += blockDim.x) s_win[i] = wp[i];
+          __syncthreads();
+          staged = j;
+        }
+      }
+    }
     if constexpr (NV > 0 && VB == 16) {
       if (idx == nullptr) {
         // identity job: the tile is one contiguous byte range; copy it as a
@@ -131,11 +156,20 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (srow[u] >= 0) {
-            const V* sp = reinterpret_cast<const V*>(src + srow[u] * rb);
+            const uint64_t wr = (uint64_t)(srow[u] - win_lo);
+            if (wr < (uint64_t)win_rows) {
 #pragma unroll
-            for (int k = 0; k < NVPL; ++k) {
-              const int vi = lane_v + k * LPR;
-              if (NV % LPR == 0 || vi < NV) v[u][k] = idx ? sp[vi] : ldv<V, NT>(sp + vi);
+              for (int k = 0; k < NVPL; ++k) {
+                const int vi = lane_v + k * LPR;
+                if (NV % LPR == 0 || vi < NV) v[u][k] = s_win[wr * NV + vi];
+              }
+            } else {
+              const V* sp = reinterpret_cast<const V*>(src + srow[u] * rb);
+#pragma unroll
+              for (int k = 0; k < NVPL; ++k) {
+                const int vi = lane_v + k * LPR;
+                if (NV % LPR == 0 || vi < NV) v[u][k] = idx ? sp[vi] : ldv<V, NT>(sp + vi);
+              }
             }
           }
         }

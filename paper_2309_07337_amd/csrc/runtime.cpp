@@ -85,6 +85,19 @@ int device_cus() {
   return cached[dev];
 }
 
+int device_lds_per_block() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 65536;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
 Sched default_sched(int kind, int row_bytes) {
   Sched s;
   s.block_threads = 256;
@@ -97,12 +110,16 @@ Sched default_sched(int kind, int row_bytes) {
   // segmented sum: the largest tile whose row pointers are staged in LDS
   if (kind == KIND_SEGSUM) rows = std::min(kStageRows, std::max(64, (64 << 10) / std::max(row_bytes, 1)));
   s.tile_rows = rows;
-  s.unroll = 4;
+  // rows in flight per lane: 4, except for rows of 16 bytes or less, whose
+  // gathers measure best with 1 (more lanes, not more rows per lane)
+  s.unroll = row_bytes <= 16 && kind == KIND_GATHER ? 1 : 4;
   if (kind == KIND_SEGSUM) s.block_threads = 512;
   // rows of 64 B and more: push by default (on gfx950 scattered full-line
   // writes run as fast as scattered reads, and the push form reads each
   // source row once instead of once per slot); short rows: pull
   s.push_pack = kind == KIND_GATHER && row_bytes >= 64 ? 1 : 0;
+  // short rows: gathers read their jobs' source windows from LDS
+  s.lds_window = kind == KIND_GATHER && row_bytes <= 16 ? 1 : 0;
   return s;
 }
 
@@ -117,6 +134,8 @@ Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
   if (p->unroll > 0) s.unroll = p->unroll <= 1 ? 1 : (p->unroll == 2 ? 2 : 4);
   if (p->push_pack == 1) s.push_pack = 1;
   else if (p->push_pack == 2) s.push_pack = 0;
+  if (p->lds_window == 1) s.lds_window = 1;
+  else if (p->lds_window == 2) s.lds_window = 0;
   return s;
 }
 
@@ -129,6 +148,7 @@ hx_sched to_public(const Sched& s) {
   o.per_neighbor = s.per_neighbor;
   o.unroll = s.unroll;
   o.push_pack = s.push_pack ? 1 : 2;
+  o.lds_window = s.lds_window ? 1 : 2;
   return o;
 }
 
@@ -227,21 +247,21 @@ static int req_phase_jobs(const hx_req* r, int phase, const Sched& sc, std::vect
                                  r->n_local});
         break;
       }
-      GatherJob j{r->x, r->send.as<char>(), r->s1_idx.as<int32_t>(), r->E1};
+      GatherJob j{r->x, r->send.as<char>(), r->s1_idx.as<int32_t>(), r->E1, 0, r->n_local};
       if (per_nbr) split_gather_by_counts(j, r->s1_counts, rb, g);
       else g->push_back(j);
       break;
     }
     case PH_REDIST: {
       GatherJob j{r->recv.as<char>(), r->send.as<char>() + r->E1 * (int64_t)rb, r->s2_src.as<int32_t>(),
-                  r->E2};
+                  r->E2, 0, r->R1};
       if (per_nbr) split_gather_by_counts(j, r->s2_counts, rb, g);
       else g->push_back(j);
       break;
     }
     case PH_UNPACK: {
       GatherJob j{r->recv.as<char>(), r->halo, r->unpack_identity ? nullptr : r->unpack_src.as<int32_t>(),
-                  r->H};
+                  r->H, 0, r->R1 + r->R2};
       if (per_nbr && r->unpack_identity) split_gather_by_counts(j, r->r1_counts, rb, g);
       else g->push_back(j);
       break;
@@ -585,11 +605,16 @@ static bool cache_lookup(const std::string& key, Sched* out) {
   if (!path) return false;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   std::ifstream f(path);
-  std::string k;
-  Sched s;
+  std::string line;
   bool found = false;
-  while (f >> k >> s.tile_rows >> s.block_threads >> s.blocks_per_cu >> s.nontemporal >> s.per_neighbor >> s.unroll >>
-         s.push_pack) {
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    Sched s;
+    if (!(ls >> k >> s.tile_rows >> s.block_threads >> s.blocks_per_cu >> s.nontemporal >> s.per_neighbor >>
+          s.unroll >> s.push_pack))
+      continue;
+    if (!(ls >> s.lds_window)) s.lds_window = 0;  // lines written before the field existed
     if (k == key) { *out = s; found = true; }
   }
   return found;
@@ -601,7 +626,7 @@ static void cache_store(const std::string& key, const Sched& s) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   std::ofstream f(path, std::ios::app);
   f << key << ' ' << s.tile_rows << ' ' << s.block_threads << ' ' << s.blocks_per_cu << ' ' << s.nontemporal
-    << ' ' << s.per_neighbor << ' ' << s.unroll << ' ' << s.push_pack << '\n';
+    << ' ' << s.per_neighbor << ' ' << s.unroll << ' ' << s.push_pack << ' ' << s.lds_window << '\n';
 }
 
 int hx::batch_init_scheds(hx_batch* b, const hx_sched* sched) {
@@ -798,20 +823,24 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
       }
     };
     consider(best);
-    // stage 1: work per tile, rows in flight, pull vs push (pack)
+    // stage 1: work per tile, rows in flight, pull vs push (pack), LDS
+    // source windows (gathers)
     {
       const Sched s0 = best;
       for (int tf : {1, 2, 4, 8, 16, 32})
         for (int u : {1, 2, 4})
-          for (int push : {0, 1}) {
-            if (push && ph != PH_PACK) continue;
-            Sched c = s0;
-            c.tile_rows = std::max(16, base * tf / 8);
-            c.unroll = u;
-            c.push_pack = ph == PH_PACK ? push : s0.push_pack;
-            c.per_neighbor = 0;
-            consider(c);
-          }
+          for (int push : {0, 1})
+            for (int win : {0, 1}) {
+              if (push && ph != PH_PACK) continue;
+              if (win && (ph == PH_BWD || push)) continue;
+              Sched c = s0;
+              c.tile_rows = std::max(16, base * tf / 8);
+              c.unroll = u;
+              c.push_pack = ph == PH_PACK ? push : s0.push_pack;
+              c.lds_window = ph == PH_BWD ? s0.lds_window : win;
+              c.per_neighbor = 0;
+              consider(c);
+            }
     }
     // stage 2: launch shape and streaming hints
     {

@@ -154,34 +154,53 @@ int world_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
                                     b->wp_idx.as<int32_t>(), b->row_starts[r + 1] - r0}});
           }
         }
-      } else if (merged) {
+      } else if (merged && !sc.lds_window) {
         g->push_back({GatherJob{b->x_global, (char*)sa, b->gidx_pack.as<int32_t>(), b->E1_tot}});
       } else {
+        // one job per rank: its indices stay inside its own rows (the window)
+        std::vector<GatherJob> v;
         for (int r = 0; r < b->R; ++r)
-          g->push_back({GatherJob{b->x_global, (char*)sa + b->s1_off[r] * rb, b->gidx_pack.as<int32_t>() + b->s1_off[r],
-                                  b->s1_off[r + 1] - b->s1_off[r]}});
+          v.push_back(GatherJob{b->x_global, (char*)sa + b->s1_off[r] * rb, b->gidx_pack.as<int32_t>() + b->s1_off[r],
+                                b->s1_off[r + 1] - b->s1_off[r], b->row_starts[r],
+                                b->row_starts[r + 1] - b->row_starts[r]});
+        if (merged) g->push_back(v);
+        else for (auto& x : v) g->push_back({x});
       }
       break;
     case PH_REDIST:
-      if (merged) {
+      if (merged && !sc.lds_window) {
         g->push_back({GatherJob{ra, (char*)sa + b->E1_tot * rb, b->gidx_redist.as<int32_t>(), b->E2_tot}});
       } else {
+        // one job per rank: it forwards values from its own stage-1 receive arena
+        std::vector<GatherJob> v;
         for (int r = 0; r < b->R; ++r)
-          g->push_back({GatherJob{ra, (char*)sa + (b->E1_tot + b->s2_off[r]) * rb,
-                                  b->gidx_redist.as<int32_t>() + b->s2_off[r], b->s2_off[r + 1] - b->s2_off[r]}});
+          v.push_back(GatherJob{ra, (char*)sa + (b->E1_tot + b->s2_off[r]) * rb,
+                                b->gidx_redist.as<int32_t>() + b->s2_off[r], b->s2_off[r + 1] - b->s2_off[r],
+                                b->r1_off[r], b->r1_off[r + 1] - b->r1_off[r]});
+        if (merged) g->push_back(v);
+        else for (auto& x : v) g->push_back({x});
       }
       break;
     case PH_UNPACK:
-      if (merged) {
+      if (merged && (b->unpack_identity || !sc.lds_window)) {
         g->push_back({GatherJob{ra, b->halo_all, b->unpack_identity ? nullptr : b->gidx_unpack.as<int32_t>(),
                                 b->H_tot}});
-      } else {
+      } else if (!b->unpack_identity) {
+        // one job per rank; its window is its stage-2 receive arena, where
+        // nearly all of its halo comes from (entries from the stage-1 arena
+        // read global memory)
+        std::vector<GatherJob> v;
         for (int r = 0; r < b->R; ++r) {
           const int64_t h0 = b->halo_off[r], h = b->halo_off[r + 1] - h0;
-          if (b->unpack_identity)
-            g->push_back({GatherJob{ra + h0 * rb, b->halo_all + h0 * rb, nullptr, h}});
-          else
-            g->push_back({GatherJob{ra, b->halo_all + h0 * rb, b->gidx_unpack.as<int32_t>() + h0, h}});
+          v.push_back(GatherJob{ra, b->halo_all + h0 * rb, b->gidx_unpack.as<int32_t>() + h0, h,
+                                b->R1_tot + b->r2_off[r], b->r2_off[r + 1] - b->r2_off[r]});
+        }
+        if (merged) g->push_back(v);
+        else for (auto& x : v) g->push_back({x});
+      } else {
+        for (int r = 0; r < b->R; ++r) {  // plain world, one launch per rank
+          const int64_t h0 = b->halo_off[r], h = b->halo_off[r + 1] - h0;
+          g->push_back({GatherJob{ra + h0 * rb, b->halo_all + h0 * rb, nullptr, h}});
         }
       }
       break;

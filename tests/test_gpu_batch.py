@@ -57,7 +57,10 @@ SCHEDS = [None,
           dict(tile_rows=17, block_threads=512, blocks_per_cu=2, nontemporal=1, per_neighbor=1, unroll=4,
                push_pack=1),
           dict(tile_rows=333, block_threads=256, blocks_per_cu=4, nontemporal=1, unroll=4, push_pack=1),
-          dict(tile_rows=2048, block_threads=256, blocks_per_cu=2, unroll=2, push_pack=1)]
+          dict(tile_rows=2048, block_threads=256, blocks_per_cu=2, unroll=2, push_pack=1),
+          dict(tile_rows=50, block_threads=512, blocks_per_cu=2, unroll=2, push_pack=2, lds_window=1),
+          dict(tile_rows=3000, unroll=4, push_pack=2, lds_window=1, per_neighbor=1),
+          dict(tile_rows=256, push_pack=2, lds_window=2)]
 
 
 @pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f32", 1), ("f64", 1), ("f32", 64)])

@@ -41,7 +41,10 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
     plan = gpu_plan(rs, rp, cols, ppn, variant)
     H = sum(h.size for h in halos)
     variants = [(False, None), (True, None), (False, dict(push_pack=1, unroll=4, tile_rows=77)),
-                (False, dict(push_pack=2, unroll=2, nontemporal=1))]
+                (False, dict(push_pack=2, unroll=2, nontemporal=1)),
+                (False, dict(push_pack=2, lds_window=1, tile_rows=64, unroll=2)),
+                (True, dict(push_pack=2, lds_window=1, unroll=1)),
+                (False, dict(push_pack=2, lds_window=2, tile_rows=5000))]
     for plain_launch, sched in variants:
         b, halo = run_world(plan, x, H, plain_launch, sched)
         got = host(halo)
