@@ -250,6 +250,25 @@ def time_steps(torch, P, batch, steps, warmup, plain, phases):
     return wall / steps * 1e3, ph
 
 
+def time_kernels(torch, P, batch, reps, phases):
+    """Average duration of each phase's kernel launched alone: events on the
+    current stream around `reps` back-to-back launches (queued faster than
+    they run, so the host's launch cost stays hidden)."""
+    P.hx_batch_wait(batch)
+    out = {}
+    for p in phases:
+        P.hx_batch_launch_phase(batch, p)
+        torch.cuda.synchronize()
+        a, c = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            P.hx_batch_launch_phase(batch, p)
+        c.record()
+        torch.cuda.synchronize()
+        out[p] = a.elapsed_time(c) / reps
+    return out
+
+
 def cpu_baseline(setup, budget_s):
     """The oracle as it stands (numpy, one thread) on the same plans and the
     same byte accounting: pack, identity unpack and fixed-order backward per
@@ -323,19 +342,19 @@ def main():
             log(f"plain:   {plain_ms:.3f} ms/step; phases (ms) {json.dumps({k: round(v, 4) for k, v in pph.items()})}")
     step_bytes = sum(v for ph_id, v in nbytes.items() if ph_id != 3 or 3 in S["phases"])
     value = step_bytes / (ms * 1e-3) / 1e9
-    # dominant kernel: the longest single-kernel phase graph (Wait holds two
-    # kernels when there is a redistribution stage, so it is not a candidate then)
-    per = {"pack": (ph["start"], nbytes[0])}
-    if 3 in S["phases"]:
-        per["backward"] = (ph["backward"], nbytes[3])
-    if nbytes[1] == 0:
-        per["unpack"] = (ph["wait"], nbytes[2])
-    dom = max(per, key=lambda k: per[k][0])
-    d_ms, d_bytes = per[dom]
-    achieved = d_bytes / (d_ms * 1e-3) / 1e9
-    kname = {"pack": "k_pack", "unpack": "k_unpack", "backward": "k_segsum"}[dom]
+    # dominant kernel: each phase's persistent kernel timed alone (same launch
+    # table as the graphs, same stream), the longest one of the step
+    names = {0: "pack", 1: "redist", 2: "unpack", 3: "backward"}
+    with torch.cuda.stream(stream):
+        kms = time_kernels(torch, P, b, max(5, args.steps // 2), [p for p in (0, 1, 2, 3) if nbytes[p] > 0])
+    step_k = {p: t for p, t in kms.items() if p != 3 or 3 in S["phases"]}
+    dom_p = max(step_k, key=lambda p: step_k[p])
+    dom = names[dom_p]
+    achieved = nbytes[dom_p] / (kms[dom_p] * 1e-3) / 1e9
+    kname = {"pack": "k_pack", "redist": "k_redist", "unpack": "k_unpack", "backward": "k_segsum"}[dom]
     if dom == "pack" and P.hx_batch_get_sched(b, 0)["push_pack"] == 1:
         kname = "k_pack_push"
+    log(f"kernels alone (ms): {json.dumps({names[p]: round(t, 4) for p, t in kms.items()})}")
     traffic = read_traffic(kname, args.workload)
     cpu = cpu_baseline(S, args.cpu_seconds) if S["host"] else None
     out = {
@@ -346,6 +365,7 @@ def main():
         "config": S["cfg"],
         "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
         "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+        "kernel_ms": {names[p]: round(t, 4) for p, t in kms.items()},
         "phase_bytes": {"pack": nbytes[0], "redist": nbytes[1], "unpack": nbytes[2], "backward": nbytes[3]},
         "fwd_gbps": round((nbytes[0] + nbytes[1] + nbytes[2]) / ((ph["start"] + ph["wait"]) * 1e-3) / 1e9, 2),
         "bwd_gbps": round(nbytes[3] / (ph["backward"] * 1e-3) / 1e9, 2) if ph["backward"] > 0 else None,

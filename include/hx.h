@@ -272,6 +272,14 @@ int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out);
 int hx_batch_backward(hx_batch* b, void* stream);
 int hx_batch_backward_plain(hx_batch* b, void* stream);
 int hx_batch_tune(hx_batch* b, void* stream);
+/* hx_batch_launch_phase: launch the persistent kernel of one phase alone
+ *   (0 pack, 1 redistribution, 2 unpack, 3 backward) from the same launch
+ *   table the graphs replay, outside the Start/Wait state machine, so that a
+ *   caller can time each kernel; the simulated transfers are not run.
+ *   HX_ERR_STATE while a Start is pending, or for the backward before
+ *   gradients are bound (members: before the first hx_batch_backward after
+ *   binding). */
+int hx_batch_launch_phase(hx_batch* b, int phase, void* stream);
 /* The schedule in use for a phase (0 pack, 1 redistribution, 2 unpack, 3 backward). */
 int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out);
 /* World arenas: which = HX_ARENA_SEND / HX_ARENA_RECV, all ranks concatenated

@@ -39,7 +39,7 @@ EXPORTED = (
     "hx_req_bind_grad", "hx_backward", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
     "hx_batch_start", "hx_batch_wait", "hx_batch_start_plain", "hx_batch_wait_plain",
     "hx_batch_bind_grad", "hx_batch_backward", "hx_batch_backward_plain", "hx_batch_tune",
-    "hx_batch_get_sched", "hx_batch_arena", "hx_batch_arena_offset", "hx_batch_bytes",
+    "hx_batch_launch_phase", "hx_batch_get_sched", "hx_batch_arena", "hx_batch_arena_offset", "hx_batch_bytes",
     "hx_batch_free",
 )
 
@@ -105,6 +105,7 @@ def load() -> C.CDLL:
         "hx_batch_backward": (C.c_int, [VP, VP]),
         "hx_batch_backward_plain": (C.c_int, [VP, VP]),
         "hx_batch_tune": (C.c_int, [VP, VP]),
+        "hx_batch_launch_phase": (C.c_int, [VP, C.c_int, VP]),
         "hx_batch_get_sched": (C.c_int, [VP, C.c_int, C.POINTER(hx_sched)]),
         "hx_batch_arena": (C.c_int, [VP, C.c_int, PP, I64P]),
         "hx_batch_arena_offset": (C.c_int, [VP, C.c_int, C.c_int, I64P]),
@@ -348,6 +349,10 @@ def hx_batch_backward(b: Batch, stream=None) -> None:
 
 def hx_batch_backward_plain(b: Batch, stream=None) -> None:
     _check(load().hx_batch_backward_plain(b.ptr, _stream(stream)))
+
+
+def hx_batch_launch_phase(b: Batch, phase: int, stream=None) -> None:
+    _check(load().hx_batch_launch_phase(b.ptr, phase, _stream(stream)))
 
 
 def hx_batch_tune(b: Batch, stream=None) -> None:

@@ -765,6 +765,23 @@ extern "C" int hx_batch_backward_plain(hx_batch* b, void* stream) {
 
 int hx::batch_run_backward(hx_batch* b, hipStream_t s) { return run_backward(b, s, false); }
 
+// One phase's persistent kernel on its own, launched directly from the same
+// launch table the graphs replay (for per-kernel timing).
+extern "C" int hx_batch_launch_phase(hx_batch* b, int phase, void* stream) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (phase < 0 || phase > 3) return fail(HX_ERR_ARG, "bad phase %d", phase);
+  if (b->active) return fail(HX_ERR_STATE, "batch active: call hx_batch_wait first");
+  if (phase == PH_BWD) {
+    if (b->world && !b->g_out) return fail(HX_ERR_STATE, "no gradient buffers bound");
+    if (!b->world) {
+      int64_t rows = 0;
+      for (hx_req* r : b->members) rows += (r->g_x ? r->n_local : 0);
+      if (rows != b->bwd_rows_captured) return fail(HX_ERR_STATE, "gradients bound after the last backward: call hx_batch_backward once first");
+    }
+  }
+  return launch_table(b->lt[phase], (hipStream_t)stream);
+}
+
 extern "C" int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out) {
   if (!b || !out || phase < 0 || phase > 3) return fail(HX_ERR_ARG, "bad argument");
   *out = to_public(b->sched[phase]);

@@ -143,3 +143,39 @@ def test_rank_requests_from_plan(variant):
         assert bits_equal(send, np.concatenate([out["send1"][r], out["send2"][r]]))
         assert bits_equal(host(halo), out["halo"][r])
         req.free()
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+def test_launch_phase_matches_graphs(variant):
+    """Each phase's kernel launched alone rewrites exactly what the graphs wrote."""
+    need_gpu()
+    import torch
+    n, R, mx, pf, seed, uneven, ppn = case = CASES[4]
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    say("launch_phase", variant, case)
+    halos = OP.all_halos(rp, cols, rs)
+    H = sum(h.size for h in halos)
+    C = 3
+    x = dev(uniform_pm1(seed, n * C).reshape(n, C))
+    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    b, halo = run_world(plan, x, H)
+    g_halo = dev(uniform_pm1(seed + 1, H * C).reshape(H, C))
+    g_x = torch.full_like(x, float("nan"))
+    P.hx_batch_bind_grad(b, g_halo, g_x)
+    P.hx_batch_backward(b)
+    send_v = P.batch_arena_view(b, P.HX_ARENA_SEND, C, torch.float64)
+    ref_send, ref_halo, ref_gx = host(send_v).copy(), host(halo).copy(), host(g_x).copy()
+    send_v.fill_(float("nan"))
+    halo.fill_(float("nan"))
+    g_x.fill_(float("nan"))
+    for ph in range(4):
+        P.hx_batch_launch_phase(b, ph)
+    torch.cuda.synchronize()
+    assert bits_equal(host(send_v), ref_send)
+    assert bits_equal(host(halo), ref_halo)
+    assert bits_equal(host(g_x), ref_gx)
+    P.hx_batch_start(b)
+    with pytest.raises(P.HXError):
+        P.hx_batch_launch_phase(b, 0)
+    P.hx_batch_wait(b)
+    b.free()
