@@ -11,6 +11,49 @@
 namespace hx {
 namespace {
 
+// bad[j] = 1 when some index of job j lies outside its source window.
+__global__ void __launch_bounds__(256) k_check_windows(const GatherJob* __restrict__ jobs, int njobs,
+                                                       int32_t* __restrict__ bad) {
+  for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+    const GatherJob g = jobs[j];
+    int out = 0;
+    if (g.win_rows > 0 && g.idx != nullptr) {
+      for (int64_t e = threadIdx.x; e < g.nrows; e += blockDim.x) {
+        const int64_t v = g.idx[e];
+        out |= (v < g.win_lo || v >= g.win_lo + g.win_rows) ? 1 : 0;
+      }
+    }
+    out = __syncthreads_or(out);
+    if (threadIdx.x == 0) bad[j] = out ? 1 : 0;
+  }
+}
+
+// Clears the windows of jobs whose indices leave them (device-side check).
+int drop_bad_windows(std::vector<GatherJob>* w) {
+  std::vector<int> at;
+  for (size_t i = 0; i < w->size(); ++i)
+    if ((*w)[i].win_rows > 0 && (*w)[i].nrows > 0) at.push_back((int)i);
+  if (at.empty()) return HX_SUCCESS;
+  std::vector<GatherJob> sub;
+  for (int i : at) sub.push_back((*w)[i]);
+  DevMem d_jobs, d_bad;
+  HX_TRY(upload_vec(d_jobs, sub));
+  HX_TRY(d_bad.alloc(sub.size() * sizeof(int32_t)));
+  const int grid = (int)std::min<size_t>(sub.size(), 4096);
+  hipLaunchKernelGGL(k_check_windows, dim3(grid), dim3(256), 0, 0, d_jobs.as<GatherJob>(), (int)sub.size(),
+                     d_bad.as<int32_t>());
+  HX_HIP(hipGetLastError());
+  std::vector<int32_t> bad(sub.size(), 1);
+  HX_HIP(hipMemcpy(bad.data(), d_bad.p, bad.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (size_t k = 0; k < at.size(); ++k) {
+    if (bad[k]) {
+      (*w)[at[k]].win_lo = 0;
+      (*w)[at[k]].win_rows = 0;
+    }
+  }
+  return HX_SUCCESS;
+}
+
 // Vector width usable for a table: divides row_bytes and every base pointer.
 int pick_vec(int row_bytes, uintptr_t align_or) {
   for (int vb : {16, 8, 4}) {
@@ -81,17 +124,20 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
   }
   // source windows: kept where the schedule asks for them and they fit
   std::vector<GatherJob> w(jobs);
-  int64_t win_bytes = 0;
   const int64_t win_cap = std::min<int64_t>(kWinBytes, device_lds_per_block());
   for (auto& j : w) {
     const int64_t bytes = j.win_rows * (int64_t)row_bytes;
     if (!s.lds_window || j.idx == nullptr || j.win_rows <= 0 || bytes > win_cap || j.win_lo < 0) {
       j.win_lo = 0;
       j.win_rows = 0;
-    } else {
-      a |= (uintptr_t)(j.src + j.win_lo * (int64_t)row_bytes);
-      win_bytes = std::max(win_bytes, bytes);
     }
+  }
+  HX_TRY(drop_bad_windows(&w));
+  int64_t win_bytes = 0;
+  for (const auto& j : w) {
+    if (j.win_rows <= 0) continue;
+    a |= (uintptr_t)(j.src + j.win_lo * (int64_t)row_bytes);
+    win_bytes = std::max(win_bytes, j.win_rows * (int64_t)row_bytes);
   }
   HX_TRY(build_table(w, KIND_GATHER, dtype, row_bytes, s, t, a));
   // (the runtime-row-size kernel form ignores windows and reads global memory)

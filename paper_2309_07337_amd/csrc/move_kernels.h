@@ -74,12 +74,12 @@ __device__ __forceinline__ int find_job(const int64_t* __restrict__ ts, int njob
 // (NV = 0: runtime nv, then U must be 1), LPR lanes per row.
 // ---------------------------------------------------------------------------
 // Source windows (use_win != 0, fixed shapes only): a job with win_rows > 0
-// reads only source rows [win_lo, win_lo + win_rows), and the table's
-// dynamic LDS holds that many rows.  The workgroup copies the window into
-// LDS with coalesced loads when it reaches a new such job and then gathers
-// from LDS: one wide read of the window instead of one L2 request per
-// (usually short, scattered) row.  Indices outside the window read global
-// memory.
+// reads only source rows [win_lo, win_lo + win_rows) (the table builder
+// checks every index on the device and drops windows that do not hold), and
+// the table's dynamic LDS holds that many rows.  The workgroup copies the
+// window into LDS with coalesced loads when it reaches a new such job and
+// then gathers from LDS: one wide read of the window instead of one L2
+// request per (usually short, scattered) row.
 template <int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
                                             int njobs, int64_t ntiles, int tile_rows, int nv_rt, int use_win) {
@@ -114,7 +114,20 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
           __syncthreads();  // every lane is done with the previous window
           const V* __restrict__ wp = reinterpret_cast<const V*>(src + win_lo * (int64_t)rb);
           const int nvec = (int)win_rows * NV;
-          for (int i = threadIdx.x; i < nvec; i += blockDim.x) s_win[i] = wp[i];
+          constexpr int UW = 8;  // loads in flight per lane while staging
+          for (int i0 = threadIdx.x; i0 < nvec; i0 += blockDim.x * UW) {
+            V w[UW];
+#pragma unroll
+            for (int u = 0; u < UW; ++u) {
+              const int i = i0 + u * blockDim.x;
+              if (i < nvec) w[u] = wp[i];
+            }
+#pragma unroll
+            for (int u = 0; u < UW; ++u) {
+              const int i = i0 + u * blockDim.x;
+              if (i < nvec) s_win[i] = w[u];
+            }
+          }
           __syncthreads();
           staged = j;
         }
@@ -145,38 +158,45 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
       }
     }
     if constexpr (NV > 0) {
+      // Lanes past the tile's end re-read its last row, so every index and
+      // row load is valid and the U loads of a lane go out together (no
+      // branch between them); only the stores are predicated.  Every index
+      // of a windowed job lies in its window (checked when the table was
+      // built).
+      const bool in_lds = win_rows > 0;
       for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * U) {
         V v[U][NVPL];
         int64_t srow[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int64_t r = base + (int64_t)u * rows_per_pass;
-          srow[u] = (r < r1) ? (idx ? (int64_t)ldv<int32_t, NT>(idx + r) : r) : -1;
+          const int64_t r = min(base + (int64_t)u * rows_per_pass, r1 - 1);
+          srow[u] = idx ? (int64_t)ldv<int32_t, NT>(idx + r) : r;
         }
+        if (in_lds) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (srow[u] >= 0) {
-            const uint64_t wr = (uint64_t)(srow[u] - win_lo);
-            if (wr < (uint64_t)win_rows) {
+          for (int u = 0; u < U; ++u) {
+            const int64_t wr = srow[u] - win_lo;
 #pragma unroll
-              for (int k = 0; k < NVPL; ++k) {
-                const int vi = lane_v + k * LPR;
-                if (NV % LPR == 0 || vi < NV) v[u][k] = s_win[wr * NV + vi];
-              }
-            } else {
-              const V* sp = reinterpret_cast<const V*>(src + srow[u] * rb);
+            for (int k = 0; k < NVPL; ++k) {
+              const int vi = lane_v + k * LPR;
+              if (NV % LPR == 0 || vi < NV) v[u][k] = s_win[wr * NV + vi];
+            }
+          }
+        } else {
 #pragma unroll
-              for (int k = 0; k < NVPL; ++k) {
-                const int vi = lane_v + k * LPR;
-                if (NV % LPR == 0 || vi < NV) v[u][k] = idx ? sp[vi] : ldv<V, NT>(sp + vi);
-              }
+          for (int u = 0; u < U; ++u) {
+            const V* sp = reinterpret_cast<const V*>(src + srow[u] * rb);
+#pragma unroll
+            for (int k = 0; k < NVPL; ++k) {
+              const int vi = lane_v + k * LPR;
+              if (NV % LPR == 0 || vi < NV) v[u][k] = idx ? sp[vi] : ldv<V, NT>(sp + vi);
             }
           }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t r = base + (int64_t)u * rows_per_pass;
-          if (srow[u] >= 0) {
+          if (r < r1) {
             V* dp = reinterpret_cast<V*>(dst + r * rb);
 #pragma unroll
             for (int k = 0; k < NVPL; ++k) {
