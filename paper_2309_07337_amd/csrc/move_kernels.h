@@ -280,25 +280,24 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
         // entry-parallel: LPR lanes per entry, U entries per lane; entries of
         // one row sit next to each other, so its reads coalesce or hit L2
         for (int base = rsub; base < ne; base += rows_per_pass * U) {
+          // lanes past the last entry re-read it (valid loads, no branch
+          // between a lane's U loads); only the stores are predicated
           V v[U][NVPL];
           int32_t dsl[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int e = base + u * rows_per_pass;
-            dsl[u] = -1;
-            if (e < ne) {
-              dsl[u] = s_idx[e];
-              const V* sp = reinterpret_cast<const V*>(in + (r0 + s_row[e]) * (int64_t)rb);
+            const int e = min(base + u * rows_per_pass, ne - 1);
+            dsl[u] = s_idx[e];
+            const V* sp = reinterpret_cast<const V*>(in + (r0 + s_row[e]) * (int64_t)rb);
 #pragma unroll
-              for (int k = 0; k < NVPL; ++k) {
-                const int vi = lane_v + k * LPR;
-                if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
-              }
+            for (int k = 0; k < NVPL; ++k) {
+              const int vi = lane_v + k * LPR;
+              if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
             }
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            if (dsl[u] >= 0) {
+            if (base + u * rows_per_pass < ne) {
               V* dp = reinterpret_cast<V*>(out + (int64_t)dsl[u] * rb);
 #pragma unroll
               for (int k = 0; k < NVPL; ++k) {
@@ -469,14 +468,12 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
             V v[U][NVPL];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-              const int e = base + u * rows_per_pass;
-              if (e < eb) {
-                const V* sp = reinterpret_cast<const V*>(in + (int64_t)s_idx[e] * rb);
+              const int e = min(base + u * rows_per_pass, eb - 1);  // valid load, no branch
+              const V* sp = reinterpret_cast<const V*>(in + (int64_t)s_idx[e] * rb);
 #pragma unroll
-                for (int k = 0; k < NVPL; ++k) {
-                  const int vi = lane_v + k * LPR;
-                  if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
-                }
+              for (int k = 0; k < NVPL; ++k) {
+                const int vi = lane_v + k * LPR;
+                if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
               }
             }
 #pragma unroll

@@ -166,3 +166,29 @@ def test_high_fan_out(sched):
     ptr, perm = OP.transpose_csr(idx, n)
     assert bits_equal(host(g_x), OM.pack_transpose(host(g_send), ptr, perm))
     b.free()
+
+
+def test_batched256_full_size_sampled(tmp_path, monkeypatch):
+    """The benchmark workload at full size (256 plans, 34.7 M halo rows, 16
+    FP64 columns) under the default and the tuned schedules: sampled plans
+    (the smallest, the largest, and a spread between) equal the oracle."""
+    need_gpu()
+    import torch
+    monkeypatch.setenv("HX_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    say("batched256 full size: building 256 plans")
+    mem = build_members(256, 10 ** 7, 16, torch.float64)
+    hs = np.array([m["h"] for m in mem])
+    assert hs.sum() == 34_696_856
+    picks = sorted({int(hs.argmin()), int(hs.argmax()), 0, 85, 170, 255})
+    b = P.hx_batch_init([m["req"] for m in mem])
+    for tuned in (False, True):
+        if tuned:
+            P.hx_batch_tune(b)
+        say("  tuned" if tuned else "  default", [P.hx_batch_get_sched(b, ph) for ph in (0, 2, 3)])
+        reset(mem)
+        P.hx_batch_start(b)
+        P.hx_batch_wait(b)
+        P.hx_batch_backward(b)
+        torch.cuda.synchronize()
+        check_members([mem[i] for i in picks], 16, torch.float64)
+    b.free()

@@ -45,14 +45,13 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
                 (False, dict(push_pack=2, lds_window=1, tile_rows=64, unroll=2)),
                 (True, dict(push_pack=2, lds_window=1, unroll=1)),
                 (False, dict(push_pack=2, lds_window=2, tile_rows=5000))]
+    ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
+    out = OM.forward_all([D.plan(r, variant) for r in range(R)], xh, rs) if full_stages else None
     for plain_launch, sched in variants:
         b, halo = run_world(plan, x, H, plain_launch, sched)
         got = host(halo)
-        ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
         assert bits_equal(got, ref)
         if full_stages:
-            plans = [D.plan(r, variant) for r in range(R)]
-            out = OM.forward_all(plans, xh, rs)
             send = host(P.batch_arena_view(b, P.HX_ARENA_SEND, ncols, dtype))
             recv = host(P.batch_arena_view(b, P.HX_ARENA_RECV, ncols, dtype))
             for r in range(R):
