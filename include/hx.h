@@ -255,7 +255,11 @@ int hx_req_free(hx_req** req);
  * hx_batch_tune: times candidate schedules on the batch's own buffers (the
  *   candidates write the same arenas/halos a start/wait would), keeps the
  *   fastest, re-captures the graphs, and records it in the tuning cache
- *   (file named by HX_TUNE_CACHE, if set).
+ *   (file named by HX_TUNE_CACHE, if set).  Search per phase: tile size x
+ *   rows per lane x pack form x LDS windows, then launch shape x streaming
+ *   hints, then the first dimensions again; each candidate is the average of
+ *   three back-to-back launches, best of two trials.  With HX_TUNE_LOG set,
+ *   every candidate's time goes to stderr.
  * ------------------------------------------------------------------------- */
 enum { HX_WORLD_SIM_TRANSFER = 1 };
 int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, hx_batch** out);
