@@ -13,13 +13,16 @@ Contents (each function cites the passage it follows):
               locality-aware 2-step plan (node dedup + on-node redistribution)
               and the transpose CSR used by the backward.
 * ``move``  : pack, simulated transfer, redistribution pack, unpack, the
-              fixed-order transpose sum (backward), and the plain definitions
-              they must reproduce (direct global gather, closed-form adjoint).
+              fixed-order transpose sum (backward), the backward taken
+              through the plan's stages, and the plain definitions they must
+              reproduce (direct global gather, closed-form adjoint).
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against brute force on tiny inputs, closed forms of the stencil workloads,
 invariants (symmetry, conservation, exactly-once delivery, dedup = unique
-count) and special cases (one rank per node == plain; one node == no
-inter-node traffic).  No function is "parity unpinned".
+count), special cases (one rank per node == plain; one node == no
+inter-node traffic; the staged backward of the plain plan == the closed-form
+adjoint) and, for the staged backward's summation order, a symbolic brute
+force written from the reading alone.  No function is "parity unpinned".
 """
 from . import plan, move  # noqa: F401

@@ -118,3 +118,74 @@ def exchange_adjoint_reference(halos: list, g_halos: list, n: int) -> np.ndarray
     ptr = np.zeros(n + 1, np.int64)
     np.cumsum(counts, out=ptr[1:])
     return segmented_sum_fixed_order(vals, ptr, order)
+
+
+def reverse_transfer(recv_bufs: list, send_lists: list, recv_lists: list) -> list:
+    """Adjoint of ``transfer``: every message travels back from its receiver's
+    slots to its sender's slots (the same segments, the roles swapped)."""
+    return transfer(recv_bufs, recv_lists, send_lists)
+
+
+def staged_adjoint_reference(plans: list, g_halos: list, row_starts) -> dict:
+    """Backward of the exchange taken through its stages in reverse (reading
+    R15; the forward is Listing 4's Start/Wait with the locality-aware
+    forwarding of Sec. 2.2):
+
+    1. unpack, reversed: a receive slot read by the rank's own halo takes
+       that entry's gradient (each slot is read by at most one halo entry);
+    2. the stage-2 messages travel back (forwarder's redistribution slots);
+    3. forwarder sums: a stage-1 receive slot k of rank q gets its own-halo
+       term first (when q's halo reads k), then the gradients of the
+       redistribution entries e with s2_src[e] == k in ascending e
+       (= ascending destination rank);
+    4. the stage-1 messages travel back;
+    5. owner sums: gX_r[i] = sum of the stage-1 send-slot gradients packed
+       from row i, in ascending slot (the pack transpose).
+
+    Sums are sequential in the gradient dtype (``segmented_sum_fixed_order``).
+    For the plain plan stages 2 and 3 are empty and the result is the
+    closed-form adjoint of ``exchange_adjoint_reference``.
+    """
+    from .plan import transpose_csr
+    R = len(plans)
+    rs = np.asarray(row_starts, np.int64)
+    tail = g_halos[0].shape[1:] if R else ()
+    dt = g_halos[0].dtype if R else np.float64
+    own, g_recv2 = [], []
+    for r in range(R):
+        p = plans[r]
+        R1 = int(np.sum(p["r1_counts"], dtype=np.int64))
+        R2 = int(np.sum(p["r2_counts"], dtype=np.int64))
+        us = np.asarray(p["unpack_src"], np.int64)
+        o = np.full(R1 + R2, -1, np.int64)
+        if np.any(np.bincount(us, minlength=R1 + R2) > 1):
+            raise AssertionError(f"rank {r}: a receive slot is read twice by the halo")
+        o[us] = np.arange(us.size)
+        if np.any(o[R1:] < 0):
+            raise AssertionError(f"rank {r}: a stage-2 slot is not read by the halo")
+        own.append(o)
+        g_recv2.append(np.asarray(g_halos[r])[o[R1:]] if R2 else np.zeros((0,) + tail, dt))
+    g_send2 = reverse_transfer(g_recv2, [(p["s2_procs"], p["s2_counts"], p["s2_displs"]) for p in plans],
+                               [(p["r2_procs"], p["r2_counts"], p["r2_displs"]) for p in plans])
+    g_recv1 = []
+    for r in range(R):
+        p = plans[r]
+        R1 = int(np.sum(p["r1_counts"], dtype=np.int64))
+        H = np.asarray(g_halos[r]).shape[0]
+        vals = np.concatenate([np.asarray(g_halos[r]).reshape((H,) + tail), g_send2[r]], axis=0)
+        src = np.asarray(p["s2_src"], np.int64)
+        order, ptr = [], [0]
+        for k in range(R1):
+            terms = ([int(own[r][k])] if own[r][k] >= 0 else []) + [H + int(e) for e in np.nonzero(src == k)[0]]
+            order.extend(terms)
+            ptr.append(len(order))
+        g_recv1.append(segmented_sum_fixed_order(vals, np.asarray(ptr, np.int64), np.asarray(order, np.int64)))
+    g_send1 = reverse_transfer(g_recv1, [(p["s1_procs"], p["s1_counts"], p["s1_displs"]) for p in plans],
+                               [(p["r1_procs"], p["r1_counts"], p["r1_displs"]) for p in plans])
+    gx = []
+    for r in range(R):
+        n_r = int(rs[r + 1] - rs[r])
+        ptr, perm = transpose_csr(plans[r]["s1_idx"], n_r)
+        gx.append(pack_transpose(g_send1[r], ptr, perm) if n_r else np.zeros((0,) + tail, dt))
+    g_x = np.concatenate(gx, axis=0) if R else np.zeros((0,) + tail, dt)
+    return dict(g_x=g_x, g_recv2=g_recv2, g_send2=g_send2, g_recv1=g_recv1, g_send1=g_send1)

@@ -244,3 +244,110 @@ def test_random_decompositions(n, R, mx, pf, seed, uneven, ppn):
         out = M.forward_all(plans, x, rs)
         for r in range(R):
             assert np.array_equal(out["halo"][r], x[np.asarray(brute_halo(rs, rp, cols, r), np.int64)])
+
+
+class Sym:
+    """A symbolic gradient: addition builds the expression it stands for, so
+    the order and grouping of every sum the oracle performs can be read back."""
+
+    def __init__(self, s):
+        self.s = s
+
+    def __add__(self, o):
+        return Sym(f"({self.s}+{o.s})")
+
+    def __eq__(self, o):
+        return isinstance(o, Sym) and self.s == o.s
+
+    def __repr__(self):
+        return self.s
+
+
+def _fold(terms):
+    acc = terms[0]
+    for t in terms[1:]:
+        acc = acc + t
+    return acc
+
+
+def brute_staged_expression(halos, row_starts, ppn):
+    """Expected expression of every row's gradient under reading R15, built
+    from the definitions alone: the owner p sends row c once to each on-node
+    rank that needs it and once per remote node m that needs it, to the
+    partner m*ppn + (lrank(p) mod cnt(m)); the partner sums its own need
+    first, then its node's other needers in ascending rank; the owner adds
+    its send slots in ascending destination rank."""
+    R = len(row_starts) - 1
+    needers = {}
+    for s, h in enumerate(halos):
+        for c in np.asarray(h).tolist():
+            needers.setdefault(c, []).append(s)
+    out = {}
+    for c, ss in needers.items():
+        p = int(np.searchsorted(row_starts, c, side="right") - 1)
+        node_p = p // ppn
+        slots = {}
+        for s in ss:
+            m = s // ppn
+            if m == node_p:
+                slots[s] = [s]
+            else:
+                cnt = min(ppn, R - m * ppn)
+                t = m * ppn + (p % ppn) % cnt
+                slots.setdefault(t, [])
+                slots[t].append(s)
+        terms = []
+        for dest in sorted(slots):
+            grp = sorted(slots[dest])
+            grp = ([dest] if dest in grp else []) + [s for s in grp if s != dest]
+            terms.append(_fold([Sym(f"g{s}_{c}") for s in grp]))
+        out[c] = _fold(terms)
+    return out
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("case", CASES)
+def test_staged_adjoint_order_brute_force(case, variant):
+    """Every row's gradient is the sum the reading prescribes, term for term
+    and in that grouping (symbolic values), for both plans."""
+    rs, rp, cols, halos, D = build(case)
+    n, R = int(rs[-1]), len(rs) - 1
+    ppn = case[-1] if variant == "locality" else 1   # the plain plan = one rank per node
+    plans = [D.plan(r, variant) for r in range(R)]
+    gy = [np.array([Sym(f"g{r}_{c}") for c in np.asarray(h).tolist()], dtype=object) for r, h in enumerate(halos)]
+    got = M.staged_adjoint_reference(plans, gy, rs)["g_x"]
+    want = brute_staged_expression(halos, rs, ppn)
+    for c in range(n):
+        if c in want:
+            assert got[c] == want[c], (c, got[c], want[c])
+        else:
+            assert not isinstance(got[c], Sym) and got[c] == 0
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_staged_adjoint_plain_is_closed_form(case):
+    """Plain plan: the staged backward is the closed-form adjoint, bit for bit
+    (random FP32 gradients, so the summation order is visible)."""
+    rs, rp, cols, halos, D = build(case)
+    n, R = int(rs[-1]), len(rs) - 1
+    plans = [D.plan(r, "plain") for r in range(R)]
+    gy = [uniform_pm1(50 + r, h.size * 3).astype(np.float32).reshape(h.size, 3) for r, h in enumerate(halos)]
+    got = M.staged_adjoint_reference(plans, gy, rs)["g_x"]
+    assert np.array_equal(got.view(np.uint32), M.exchange_adjoint_reference(halos, gy, n).view(np.uint32))
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_staged_adjoint_locality_exact_values(case):
+    """Locality plan: with small-integer gradients (exact in FP64 whatever the
+    order) the staged backward equals the closed-form adjoint, and it is the
+    adjoint of the forward: <G x, y> == <x, G^T y>."""
+    rs, rp, cols, halos, D = build(case)
+    n, R = int(rs[-1]), len(rs) - 1
+    plans = [D.plan(r, "locality") for r in range(R)]
+    gy = [((np.arange(h.size * 2) * 7 + 3 * r) % 13 - 6).astype(np.float64).reshape(h.size, 2)
+          for r, h in enumerate(halos)]
+    got = M.staged_adjoint_reference(plans, gy, rs)["g_x"]
+    assert np.array_equal(got, M.exchange_adjoint_reference(halos, gy, n))
+    x = (np.arange(n * 2) % 9 - 4).astype(np.float64).reshape(n, 2)
+    fw = M.forward_all(plans, x, rs)["halo"]
+    assert sum(float(np.sum(a * b)) for a, b in zip(fw, gy)) == float(np.sum(x * got))
