@@ -188,7 +188,8 @@ def setup_world(args, torch, P, name):
     halo = torch.empty(H, C, dtype=dt, device="cuda")
     g_halo = torch.ones_like(halo)
     g_x = torch.empty_like(x)
-    batch = P.hx_batch_from_plan(plan, x, halo, flags=0)
+    # locality plans take the backward through the plan's stages (each rank-local)
+    batch = P.hx_batch_from_plan(plan, x, halo, flags=0 if variant == P.HX_PLAIN else P.HX_WORLD_STAGED_BACKWARD)
     P.hx_batch_bind_grad(batch, g_halo, g_x)
     if not args.no_tune:
         P.hx_batch_tune(batch)

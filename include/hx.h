@@ -248,7 +248,17 @@ int hx_req_free(hx_req** req);
  *   stage-2 message likewise (the simulated transport; not part of the
  *   path's own work).  The world's backward is the full adjoint of the
  *   exchange: g_x[c] = sum over ranks s (ascending) whose halo holds c of
- *   g_halo_all at that entry, fixed order as hx_backward.
+ *   g_halo_all at that entry, fixed order as hx_backward.  With flags &
+ *   HX_WORLD_STAGED_BACKWARD a locality plan's backward instead runs the
+ *   forward's stages in reverse, each rank-local (same value in exact
+ *   arithmetic, another grouping of the sums): the reverse unpack scatters
+ *   g_halo_all into the receive slots; the stage-2 messages travel back;
+ *   each forwarder sums per stage-1 receive slot its own halo's term, then
+ *   its redistribution entries in ascending entry (= destination rank); the
+ *   stage-1 messages travel back; each owner sums its send slots per row in
+ *   ascending slot.  The two travels are the simulated transport (run with
+ *   HX_WORLD_SIM_TRANSFER).  Plain plans: the flag changes nothing (their
+ *   backward is already the owner sums after the reverse stage-1 travel).
  * hx_batch_start / hx_batch_wait: Start / Wait of all members (graph launch).
  * hx_batch_start_plain / hx_batch_wait_plain: the same work as one launch per
  *   member (the plain one-plan-per-launch form, for comparison).
@@ -261,7 +271,7 @@ int hx_req_free(hx_req** req);
  *   three back-to-back launches, best of two trials.  With HX_TUNE_LOG set,
  *   every candidate's time goes to stderr.
  * ------------------------------------------------------------------------- */
-enum { HX_WORLD_SIM_TRANSFER = 1 };
+enum { HX_WORLD_SIM_TRANSFER = 1, HX_WORLD_STAGED_BACKWARD = 2 };
 int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, hx_batch** out);
 int hx_batch_from_plan(const hx_plan* plan, const void* x_global, void* halo_all,
                        hx_dtype dtype, int ncols, int flags, const hx_sched* sched,

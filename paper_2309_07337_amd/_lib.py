@@ -20,7 +20,7 @@ HX_ERR_ARG, HX_ERR_RANGE, HX_ERR_STATE, HX_ERR_NOMEM, HX_ERR_UNSUPPORTED, HX_ERR
 HX_F32, HX_F64 = 0, 1
 HX_PLAIN, HX_LOCALITY_2STEP = 0, 1
 HX_ARENA_SEND, HX_ARENA_RECV, HX_ARENA_GRAD_SEND = 0, 1, 4
-HX_WORLD_SIM_TRANSFER = 1
+HX_WORLD_SIM_TRANSFER, HX_WORLD_STAGED_BACKWARD = 1, 2
 HX_PLAN_MAX_RANKS = 16384
 PHASES = ("pack", "redist", "unpack", "backward")
 

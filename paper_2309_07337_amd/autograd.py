@@ -5,7 +5,9 @@ to persistent buffers; ``HaloGather`` is the ``torch.autograd.Function``
 whose forward runs Start/Wait of all ranks (pack, simulated transfer,
 redistribution, unpack) and whose backward runs the library's fixed-order
 transpose sum: for every owned row c, the gradient is the sum over the ranks
-whose halo holds c, in ascending rank order, of that halo entry's gradient.
+whose halo holds c, in ascending rank order, of that halo entry's gradient
+(or, with ``staged_backward``, the same sum grouped by the locality plan's
+stages: each forwarder's partial sum first, see ``hx.h``).
 Both directions run in the library's HIP kernels.
 """
 from __future__ import annotations
@@ -23,12 +25,14 @@ class HaloExchange:
     """
 
     def __init__(self, plan: L.Plan, n: int, halo_rows: int, ncols: int, dtype=torch.float32,
-                 device="cuda", sim_transfer: bool = True, sched=None):
+                 device="cuda", sim_transfer: bool = True, sched=None, staged_backward: bool = False):
         self.x = torch.zeros(n, ncols, dtype=dtype, device=device)
         self.halo = torch.zeros(halo_rows, ncols, dtype=dtype, device=device)
         self.g_halo = torch.zeros_like(self.halo)
         self.g_x = torch.zeros_like(self.x)
         flags = L.HX_WORLD_SIM_TRANSFER if sim_transfer else 0
+        if staged_backward:   # locality plans: the backward through the plan's stages
+            flags |= L.HX_WORLD_STAGED_BACKWARD
         self.batch = L.hx_batch_from_plan(plan, self.x, self.halo, flags=flags, sched=sched)
         L.hx_batch_bind_grad(self.batch, self.g_halo, self.g_x)
 

@@ -74,6 +74,10 @@ __global__ void k_fill_neg(int32_t* p, int64_t n) {
   GRID_STRIDE(i, n) p[i] = -1;
 }
 
+__global__ void k_fill_zero(int32_t* p, int64_t n) {
+  GRID_STRIDE(i, n) p[i] = 0;
+}
+
 // inv[map[i]] = i for a permutation map (out-of-range targets are skipped and
 // leave -1, which the range check then reports).
 __global__ void k_invert(const int32_t* __restrict__ map, int64_t n, int32_t* inv) {
@@ -81,6 +85,45 @@ __global__ void k_invert(const int32_t* __restrict__ map, int64_t n, int32_t* in
     const int32_t t = map[i];
     if (t >= 0 && t < n) inv[t] = (int32_t)i;
   }
+}
+
+// inv[map[i] - off] = base + i for a bijection onto [off, off + n) (other
+// targets are skipped and leave -1 for the range check).
+__global__ void k_invert_off(const int32_t* __restrict__ map, int64_t n, int64_t off, int64_t base, int32_t* inv) {
+  GRID_STRIDE(i, n) {
+    const int64_t t = (int64_t)map[i] - off;
+    if (t >= 0 && t < n) inv[t] = (int32_t)(base + i);
+  }
+}
+
+__global__ void k_iota(int32_t* out, int64_t n) {
+  GRID_STRIDE(i, n) out[i] = (int32_t)i;
+}
+
+// own[k] = 1 for every stage-1 receive slot k (< R1_tot) that a halo entry
+// of its own rank reads.
+__global__ void k_mark_own(const int32_t* __restrict__ unpack, int64_t H, int64_t R1_tot, int32_t* own) {
+  GRID_STRIDE(i, H) {
+    const int32_t k = unpack[i];
+    if (k >= 0 && k < R1_tot) own[k] = 1;
+  }
+}
+
+// Forwarder-sum CSR (staged backward): the terms of stage-1 receive slot k
+// are its own-halo term (row k of the gradient arena) when own[k], then the
+// redistribution entries that read k in ascending entry (rows S + e).
+__global__ void k_forward_terms(const int32_t* __restrict__ own, const int32_t* __restrict__ gp,
+                                const int32_t* __restrict__ gperm, const int32_t* __restrict__ fptr, int64_t R1_tot,
+                                int64_t S, int32_t* fidx) {
+  GRID_STRIDE(k, R1_tot) {
+    int32_t pos = fptr[k];
+    if (own[k]) fidx[pos++] = (int32_t)k;
+    for (int32_t j = gp[k]; j < gp[k + 1]; ++j) fidx[pos++] = (int32_t)(S + gperm[j]);
+  }
+}
+
+__global__ void k_add_i32(const int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t n, int32_t* out) {
+  GRID_STRIDE(i, n) out[i] = a[i] + b[i + 1] - b[i];
 }
 
 // Unpack map in world coordinates: slot u of rank r's [stage-1 | stage-2]
@@ -206,10 +249,10 @@ int world_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
       break;
     case PH_BWD: {
       if (!b->g_out) break;
-      // plain: each rank sums the gradients of its own send slots (the reverse
-      // transfer delivered them into g_send_all); other variants: the adjoint
-      // over halo_all rows directly
-      const bool local = b->unpack_identity;
+      // plain and staged locality worlds: each rank sums the gradients of its
+      // own send slots (the reverse transfer delivered them into
+      // g_send_all); otherwise the closed-form adjoint over halo_all rows
+      const bool local = b->unpack_identity || b->staged_bwd;
       const char* in = local ? b->g_send_all.as<char>() : b->g_in;
       const int32_t* ptr = local ? b->wp_ptr.as<int32_t>() : b->wb_ptr.as<int32_t>();
       const int32_t* idx = local ? b->wp_idx.as<int32_t>() : b->wb_idx.as<int32_t>();
@@ -478,6 +521,66 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
     HX_HIP(hipGetLastError());
     HX_TRY(dev_check_range(b->gidx_back.as<int32_t>(), b->E1_tot, b->H_tot, "reverse transfer", s));
   }
+  // staged backward of a locality plan (the forward's stages reversed):
+  //   reverse unpack   G[unpack[i]] = g_halo[i]            (scatter, H rows)
+  //   reverse stage 2  G[S + e] = G[R1 + inv2[e]]          (transport)
+  //   forwarder sums   gR1[k] = sum of G[f_idx[f_ptr[k] ..]] (own term, then entries)
+  //   reverse stage 1  g_send[e] = gR1[inv1[e]]            (transport)
+  //   owner sums       g_x = pack transpose over g_send    (as the plain world)
+  // with G = [stage-1 recv | stage-2 recv | stage-2 send] gradient rows.
+  if ((flags & HX_WORLD_STAGED_BACKWARD) && !b->unpack_identity) {
+    b->staged_bwd = true;
+    const int64_t S = b->R1_tot + b->R2_tot;
+    if (b->E1_tot != b->R1_tot || b->E2_tot != b->R2_tot)
+      return fail(HX_ERR_ARG, "plan: sends and receives of a stage differ in size");
+    HX_TRY(b->gidx_back.alloc((size_t)b->E1_tot * 4));
+    HX_TRY(b->gidx_back2.alloc((size_t)b->E2_tot * 4));
+    HX_TRY(b->bwd_iota.alloc((size_t)(b->H_tot + 1) * 4));
+    if (b->E1_tot) {
+      hipLaunchKernelGGL(k_fill_neg, dim3(blocks_for(b->E1_tot)), dim3(TB), 0, s, b->gidx_back.as<int32_t>(), b->E1_tot);
+      hipLaunchKernelGGL(k_invert_off, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, b->gidx_x1.as<int32_t>(), b->R1_tot,
+                         (int64_t)0, (int64_t)0, b->gidx_back.as<int32_t>());
+    }
+    if (b->E2_tot) {
+      hipLaunchKernelGGL(k_fill_neg, dim3(blocks_for(b->E2_tot)), dim3(TB), 0, s, b->gidx_back2.as<int32_t>(),
+                         b->E2_tot);
+      hipLaunchKernelGGL(k_invert_off, dim3(blocks_for(b->R2_tot)), dim3(TB), 0, s, b->gidx_x2.as<int32_t>(),
+                         b->R2_tot, b->E1_tot, b->R1_tot, b->gidx_back2.as<int32_t>());
+    }
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(b->H_tot + 1)), dim3(TB), 0, s, b->bwd_iota.as<int32_t>(), b->H_tot + 1);
+    // forwarder-sum CSR
+    DevMem own, gp, gperm, lens;
+    HX_TRY(own.alloc((size_t)std::max<int64_t>(b->R1_tot, 1) * 4));
+    HX_TRY(gp.alloc((size_t)(b->R1_tot + 1) * 4));
+    HX_TRY(gperm.alloc((size_t)std::max<int64_t>(b->E2_tot, 1) * 4));
+    HX_TRY(lens.alloc((size_t)(b->R1_tot + 1) * 4));
+    HX_TRY(b->fwd_ptr.alloc((size_t)(b->R1_tot + 1) * 4));
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(b->R1_tot + 1)), dim3(TB), 0, s, own.as<int32_t>(), b->R1_tot);
+    if (b->H_tot)
+      hipLaunchKernelGGL(k_mark_own, dim3(blocks_for(b->H_tot)), dim3(TB), 0, s, b->gidx_unpack.as<int32_t>(), b->H_tot,
+                         b->R1_tot, own.as<int32_t>());
+    HX_HIP(hipGetLastError());
+    HX_TRY(dev_group_by_key(b->gidx_redist.as<int32_t>(), b->E2_tot, b->R1_tot, gp.as<int32_t>(), gperm.as<int32_t>(),
+                            s));
+    if (b->R1_tot)
+      hipLaunchKernelGGL(k_add_i32, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, own.as<int32_t>(), gp.as<int32_t>(),
+                         b->R1_tot, lens.as<int32_t>());
+    HX_HIP(hipGetLastError());
+    HX_TRY(dev_exclusive_scan_i32(lens.as<int32_t>(), b->fwd_ptr.as<int32_t>(), b->R1_tot, s));
+    int32_t nterms = 0;
+    HX_HIP(hipMemcpy(&nterms, b->fwd_ptr.as<int32_t>() + b->R1_tot, 4, hipMemcpyDeviceToHost));
+    b->fwd_terms = nterms;
+    HX_TRY(b->fwd_idx.alloc((size_t)std::max<int32_t>(nterms, 1) * 4));
+    if (b->R1_tot)
+      hipLaunchKernelGGL(k_forward_terms, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, own.as<int32_t>(),
+                         gp.as<int32_t>(), gperm.as<int32_t>(), b->fwd_ptr.as<int32_t>(), b->R1_tot, S,
+                         b->fwd_idx.as<int32_t>());
+    HX_HIP(hipGetLastError());
+    HX_HIP(hipDeviceSynchronize());
+    HX_TRY(dev_check_range(b->gidx_back.as<int32_t>(), b->E1_tot, b->R1_tot, "reverse stage-1 transfer", s));
+    HX_TRY(dev_check_range(b->gidx_back2.as<int32_t>(), b->E2_tot, S, "reverse stage-2 transfer", s));
+    HX_TRY(dev_check_range(b->fwd_idx.as<int32_t>(), nterms, S + b->E2_tot, "forwarder sums", s));
+  }
   // algorithmic bytes per phase
   {
     int64_t U1 = 0, U2 = 0;
@@ -488,6 +591,10 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
     b->bytes[PH_REDIST] = (b->E2_tot + U2) * rbi + 4 * b->E2_tot;
     b->bytes[PH_UNPACK] = 2 * b->H_tot * rbi + (b->unpack_identity ? 0 : 4 * b->H_tot);
     b->bytes[PH_BWD] = (b->H_tot + b->n) * rbi + 4 * (b->H_tot + b->n + 1);
+    if (b->staged_bwd)  // reverse unpack + forwarder sums + owner sums
+      b->bytes[PH_BWD] = (2 * b->H_tot * rbi + 4 * (2 * b->H_tot + 1)) +
+                         ((b->fwd_terms + b->R1_tot) * rbi + 4 * (b->fwd_terms + b->R1_tot + 1)) +
+                         ((b->E1_tot + b->n) * rbi + 4 * (b->E1_tot + b->n + 1));
   }
   HX_TRY(batch_init_scheds(b.get(), sched));
   HX_TRY(batch_prepare(b.get()));

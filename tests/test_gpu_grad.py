@@ -184,3 +184,93 @@ def test_world_backward_plain_launch_equals_graph(variant, sim):
     assert bits_equal(host(ex.g_x), g_graph)
     gy = np.split(host(g), np.cumsum([h.size for h in halos])[:-1])
     assert bits_equal(g_graph, OM.exchange_adjoint_reference(halos, gy, n))
+
+
+def staged_exchange(rs, rp, cols, ppn, variant, ncols, dtype, sim=True):
+    from paper_2309_07337_amd.autograd import HaloExchange
+    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    H = sum(int(P.hx_plan_field(plan, r, "halo").size) for r in range(len(rs) - 1))
+    return HaloExchange(plan, int(rs[-1]), H, ncols, dtype=dtype, sim_transfer=sim, staged_backward=True), plan
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("case", CASES)
+def test_staged_backward_tiny_bit_exact(case, variant):
+    """Backward through the plan's stages == the oracle's staged adjoint, bit
+    for bit, in the graph and in the one-launch-per-rank form."""
+    need_gpu()
+    import torch
+    n, R, mx, pf, seed, uneven, ppn = case
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    say("staged backward", variant, case)
+    ex, _ = staged_exchange(rs, rp, cols, ppn, variant, 3, torch.float32)
+    H = ex.halo.shape[0]
+    g = uniform_pm1_f32(seed + 31, H * 3).reshape(H, 3)
+    gy = np.split(g, np.cumsum([h.size for h in halos])[:-1])
+    want = OM.staged_adjoint_reference([D.plan(r, variant) for r in range(R)], gy, rs)["g_x"]
+    ex.g_halo.copy_(dev(g))
+    P.hx_batch_backward(ex.batch)
+    torch.cuda.synchronize()
+    assert bits_equal(host(ex.g_x), want)
+    ex.g_x.fill_(float("nan"))
+    P.hx_batch_backward_plain(ex.batch)
+    torch.cuda.synchronize()
+    assert bits_equal(host(ex.g_x), want)
+    if variant == "plain":   # the closed form, whichever flag
+        assert bits_equal(want, OM.exchange_adjoint_reference(halos, gy, n))
+
+
+def test_staged_backward_grid3d_full():
+    """27-point 128^3, 512 ranks, locality plan, 4 FP32 columns: bit-exact
+    against the oracle's staged adjoint at full size."""
+    need_gpu()
+    import torch
+    rs, rp, cols = cached_grid3d()
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, 64)
+    say("staged backward grid3d")
+    ex, _ = staged_exchange(rs, rp, cols, 64, "locality", 4, torch.float32)
+    H = ex.halo.shape[0]
+    g = uniform_pm1_f32(5, H * 4).reshape(H, 4)
+    gy = np.split(g, np.cumsum([h.size for h in halos])[:-1])
+    want = OM.staged_adjoint_reference([D.plan(r, "locality") for r in range(len(rs) - 1)], gy, rs)["g_x"]
+    ex.g_halo.copy_(dev(g))
+    P.hx_batch_backward(ex.batch)
+    torch.cuda.synchronize()
+    assert bits_equal(host(ex.g_x), want)
+
+
+def test_staged_backward_random_rows_exact_values():
+    """2^22 x 32, 4096 ranks, locality plan, 1 FP64 column: with small-integer
+    gradients every grouping is exact, so the staged backward must equal the
+    closed-form one (the library's own, checked bit-exact elsewhere) and the
+    oracle's closed form on sampled rows."""
+    need_gpu()
+    import torch
+    from paper_2309_07337_amd.autograd import HaloExchange
+    rs, rp, cols = cached_random_rows()
+    say("staged backward random_rows")
+    plan = gpu_plan(rs, rp, cols, 128, "locality")
+    R, n = len(rs) - 1, int(rs[-1])
+    H = sum(int(P.hx_plan_field(plan, r, "halo").size) for r in range(R))
+    staged = HaloExchange(plan, n, H, 1, dtype=torch.float64, staged_backward=True)
+    flat = HaloExchange(plan, n, H, 1, dtype=torch.float64)
+    g = ((torch.arange(H, dtype=torch.int64, device="cuda") * 7919) % 17 - 8).to(torch.float64).view(H, 1)
+    for ex in (staged, flat):
+        ex.g_halo.copy_(g)
+        P.hx_batch_backward(ex.batch)
+    torch.cuda.synchronize()
+    assert torch.equal(staged.g_x, flat.g_x)
+    halos = [P.hx_plan_field(plan, r, "halo").astype(np.int64) for r in range(R)]
+    allh = np.concatenate(halos)
+    gh = host(g)[:, 0]
+    rng = np.random.default_rng(3)
+    rows = rng.choice(n, 2000, replace=False)
+    got = host(staged.g_x)[:, 0]
+    order = np.argsort(allh, kind="stable")
+    sh = allh[order]
+    for c in rows:
+        lo, hi = np.searchsorted(sh, c), np.searchsorted(sh, c, side="right")
+        assert got[c] == float(np.sum(gh[order[lo:hi]]))
