@@ -74,21 +74,28 @@ struct GatherJob {
   int64_t win_rows = 0;
 };
 // out[i, :] = in[idx[ptr[i]], :] + in[idx[ptr[i]+1], :] + ... (ascending,
-// first term first; empty -> +0) for i < nrows.
+// first term first; empty -> +0) for i < nrows.  Terms t >= split come from
+// the second input instead: in2[t - split, :] (segmented sums only).
 struct SegSumJob {
   const char* in;
   char* out;
   const int32_t* ptr;
   const int32_t* idx;
   int64_t nrows;
+  const char* in2 = nullptr;
+  int32_t split = INT32_MAX;
 };
 
 // Gather: pull rows through an index (GatherJob).  Segsum: fixed-order sum
 // over the segments of a CSR (SegSumJob).  Scatter: push each row of a CSR's
 // rows to its slots (SegSumJob: in = rows, out = slots).
 enum JobKind { KIND_GATHER = 0, KIND_SEGSUM = 1, KIND_SCATTER = 2 };
-// Which phase a gather table serves (selects the kernel symbol only).
-enum GatherTag { TAG_PACK = 0, TAG_REDIST = 1, TAG_UNPACK = 2, TAG_TRANSFER = 3 };
+// Which step a table serves (selects the kernel symbol only, so profiles
+// separate the steps): gathers PACK / REDIST / UNPACK / TRANSFER, the push
+// pack (PACK), segmented sums OWNER_SUM / FWD_SUM (the staged backward's
+// forwarder sums).
+enum GatherTag { TAG_PACK = 0, TAG_REDIST = 1, TAG_UNPACK = 2, TAG_TRANSFER = 3, TAG_OWNER_SUM = 4,
+                 TAG_FWD_SUM = 5 };
 
 struct Sched {
   int tile_rows = 0;
@@ -137,9 +144,9 @@ struct LaunchTable {
 int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_bytes,
                        const Sched& s, LaunchTable* t, int tag = TAG_TRANSFER);
 int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes,
-                       const Sched& s, LaunchTable* t);
+                       const Sched& s, LaunchTable* t, int tag = TAG_OWNER_SUM);
 int build_scatter_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes,
-                        const Sched& s, LaunchTable* t);
+                        const Sched& s, LaunchTable* t, int tag = TAG_PACK);
 int launch_table(const LaunchTable& t, hipStream_t stream);
 
 // Split a gather job per message (per neighbor) using the message counts.

@@ -85,15 +85,14 @@ struct hx_batch {
   hx::DevMem g_send_all;                     // plain worlds: gradients of every rank's send slots
   hx::DevMem wb_ptr, wb_idx;                 // adjoint CSR: global column -> halo_all rows
   hx::DevMem wp_ptr, wp_idx;                 // transpose of the pack map: global row -> send_all rows
-  // staged backward of a locality world (reverse unpack, forwarder sums, owner sums)
+  // staged backward of a locality world (forwarder sums, owner sums)
   bool staged_bwd = false;
-  hx::DevMem gidx_back2;                     // stage-2 send slot -> row of g_stage holding its receiver's gradient
-  hx::DevMem bwd_iota;                       // [0, 1, ..., H]: one slot per halo row in the reverse unpack
+  hx::DevMem gidx_back2;                     // stage-2 send slot -> halo row whose gradient it carries back
   hx::DevMem fwd_ptr, fwd_idx;               // forwarder-sum CSR over stage-1 receive slots
   int64_t fwd_terms = 0;
-  hx::DevMem g_stage;                        // [stage-1 recv | stage-2 recv | stage-2 send] gradients
+  hx::DevMem g_s2;                           // gradients of every stage-2 send slot
   hx::DevMem g_r1;                           // forwarder sums (stage-1 receive slot gradients)
-  hx::LaunchTable lt_bwd[2];                 // reverse unpack, forwarder sums
+  hx::LaunchTable lt_fwd_sum;                // forwarder sums
   ~hx_batch();
 };
 

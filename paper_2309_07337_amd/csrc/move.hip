@@ -108,6 +108,7 @@ uintptr_t align_of(const std::vector<SegSumJob>& jobs, int row_bytes) {
   for (const auto& j : jobs) {
     if (j.nrows <= 0) continue;
     a |= (uintptr_t)j.in | (uintptr_t)j.out;
+    if (j.in2) a |= (uintptr_t)j.in2;
   }
   return a;
 }
@@ -146,13 +147,14 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
 }
 
 int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
-                       LaunchTable* t) {
+                       LaunchTable* t, int tag) {
+  t->tag = tag;
   return build_table(jobs, KIND_SEGSUM, dtype, row_bytes, s, t, align_of(jobs, row_bytes));
 }
 
 int build_scatter_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
-                        LaunchTable* t) {
-  t->tag = TAG_PACK;
+                        LaunchTable* t, int tag) {
+  t->tag = tag;
   return build_table(jobs, KIND_SCATTER, dtype, row_bytes, s, t, align_of(jobs, row_bytes));
 }
 

@@ -386,6 +386,12 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
 // coalesced loads, so each row then costs one dependent global access (its
 // terms) instead of three.
 
+// Address of term t of a segmented sum: row t of the first input, or row
+// t - split of the second one.
+__device__ __forceinline__ const char* term_row(const char* in, const char* in2, int32_t split, int32_t t, size_t rb) {
+  return t < split ? in + (int64_t)t * (int64_t)rb : in2 + (int64_t)(t - split) * (int64_t)rb;
+}
+
 template <class T, int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
                                             int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
@@ -406,6 +412,9 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
   for (int64_t t = t0; t < t1; ++t) {
     while (t >= ts[j + 1]) ++j;
     const char* __restrict__ in = jobs[j].in;
+    // terms t >= split are rows t - split of the second input
+    const int32_t split = jobs[j].split;
+    const char* __restrict__ in2 = jobs[j].in2;
     char* __restrict__ out = jobs[j].out;
     const int32_t* __restrict__ ptr = jobs[j].ptr;
     const int32_t* __restrict__ idx = jobs[j].idx;
@@ -451,9 +460,9 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
               for (int k = 0; k < NVPL; ++k) {
                 const int vi = lane_v + k * LPR;
                 if (NV % LPR == 0 || vi < NV) {
-                  V acc = reinterpret_cast<const V*>(in + (int64_t)s_idx[a] * rb)[vi];
+                  V acc = reinterpret_cast<const V*>(term_row(in, in2, split, s_idx[a], rb))[vi];
                   for (int32_t d = 1; d < len; ++d)
-                    acc = acc + reinterpret_cast<const V*>(in + (int64_t)s_idx[a + d] * rb)[vi];
+                    acc = acc + reinterpret_cast<const V*>(term_row(in, in2, split, s_idx[a + d], rb))[vi];
                   stv<V, NT>(dp + vi, acc);
                 }
               }
@@ -469,7 +478,7 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
               const int e = min(base + u * rows_per_pass, eb - 1);  // valid load, no branch
-              const V* sp = reinterpret_cast<const V*>(in + (int64_t)s_idx[e] * rb);
+              const V* sp = reinterpret_cast<const V*>(term_row(in, in2, split, s_idx[e], rb));
 #pragma unroll
               for (int k = 0; k < NVPL; ++k) {
                 const int vi = lane_v + k * LPR;
@@ -542,7 +551,7 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
             if (d < len[u]) {
               const int32_t e = a[u] + d;
               const int32_t src = stage_idx ? s_idx[e - P0] : ldv<int32_t, NT>(idx + e);
-              const V* sp = reinterpret_cast<const V*>(in + (int64_t)src * rb);
+              const V* sp = reinterpret_cast<const V*>(term_row(in, in2, split, src, rb));
 #pragma unroll
               for (int k = 0; k < NVPL; ++k) {
                 const int vi = lane_v + k * LPR;
@@ -579,7 +588,7 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
         for (int vi = lane_v; vi < nv; vi += LPR) {
           V acc = (V)(T)0;
           for (int32_t e = p0; e < p1; ++e) {
-            const V v = reinterpret_cast<const V*>(in + (int64_t)ldv<int32_t, NT>(idx + e) * rb)[vi];
+            const V v = reinterpret_cast<const V*>(term_row(in, in2, split, ldv<int32_t, NT>(idx + e), rb))[vi];
             acc = (e == p0) ? v : acc + v;
           }
           stv<V, NT>(dp + vi, acc);

@@ -730,20 +730,16 @@ extern "C" int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out) {
     std::vector<GatherJob> xb{GatherJob{b->g_in, b->g_send_all.as<char>(), b->gidx_back.as<int32_t>(), b->E1_tot}};
     HX_TRY(build_gather_table(xb, b->dtype, rbi, gsc, &b->lt_xfer[2]));
   } else if (b->staged_bwd) {
-    // locality world, staged: G = [stage-1 recv | stage-2 recv | stage-2 send]
-    const int64_t S = b->R1_tot + b->R2_tot;
-    HX_TRY(b->g_stage.alloc((size_t)(S + b->E2_tot) * b->row_bytes));
+    // locality world, staged: forwarder sums read the halo gradients (own
+    // terms) and the stage-2 send-slot gradients (split = H)
+    HX_TRY(b->g_s2.alloc((size_t)b->E2_tot * b->row_bytes));
     HX_TRY(b->g_r1.alloc((size_t)b->R1_tot * b->row_bytes));
     HX_TRY(b->g_send_all.alloc((size_t)b->E1_tot * b->row_bytes));
-    char* G = b->g_stage.as<char>();
-    std::vector<SegSumJob> ru{SegSumJob{b->g_in, G, b->bwd_iota.as<int32_t>(), b->gidx_unpack.as<int32_t>(), b->H_tot}};
-    Sched ssc = gsc;
-    ssc.tile_rows = std::min(ssc.tile_rows, kStageRows);
-    HX_TRY(build_scatter_table(ru, b->dtype, rbi, ssc, &b->lt_bwd[0]));
-    std::vector<SegSumJob> fs{SegSumJob{G, b->g_r1.as<char>(), b->fwd_ptr.as<int32_t>(), b->fwd_idx.as<int32_t>(),
-                                        b->R1_tot}};
-    HX_TRY(build_segsum_table(fs, b->dtype, rbi, default_sched(KIND_SEGSUM, rbi), &b->lt_bwd[1]));
-    std::vector<GatherJob> x2{GatherJob{G, G + S * (int64_t)b->row_bytes, b->gidx_back2.as<int32_t>(), b->E2_tot}};
+    SegSumJob fj{b->g_in, b->g_r1.as<char>(), b->fwd_ptr.as<int32_t>(), b->fwd_idx.as<int32_t>(), b->R1_tot};
+    fj.in2 = b->g_s2.as<char>();
+    fj.split = (int32_t)b->H_tot;
+    HX_TRY(build_segsum_table({fj}, b->dtype, rbi, default_sched(KIND_SEGSUM, rbi), &b->lt_fwd_sum, TAG_FWD_SUM));
+    std::vector<GatherJob> x2{GatherJob{b->g_in, b->g_s2.as<char>(), b->gidx_back2.as<int32_t>(), b->E2_tot}};
     HX_TRY(build_gather_table(x2, b->dtype, rbi, gsc, &b->lt_xfer[3]));
     std::vector<GatherJob> x1{GatherJob{b->g_r1.as<char>(), b->g_send_all.as<char>(), b->gidx_back.as<int32_t>(),
                                         b->E1_tot}};
@@ -754,14 +750,13 @@ extern "C" int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out) {
 
 // Backward of a batch.  Plain worlds: with the simulated transport the
 // reverse stage-1 transfer first, then the owner sums.  Staged locality
-// worlds: reverse unpack, [reverse stage-2 transfer], forwarder sums,
-// [reverse stage-1 transfer], owner sums.  Others: the fixed-order sums.
+// worlds: [reverse stage-2 transfer], forwarder sums, [reverse stage-1
+// transfer], owner sums.  Others: the fixed-order sums.
 static int run_backward(hx_batch* b, hipStream_t s, bool plain_form) {
   const bool sim = b->world && (b->flags & HX_WORLD_SIM_TRANSFER);
   if (b->world && b->staged_bwd) {
-    HX_TRY(launch_table(b->lt_bwd[0], s));
     if (sim) HX_TRY(launch_table(b->lt_xfer[3], s));
-    HX_TRY(launch_table(b->lt_bwd[1], s));
+    HX_TRY(launch_table(b->lt_fwd_sum, s));
     if (sim) HX_TRY(launch_table(b->lt_xfer[2], s));
   } else if (b->world && b->unpack_identity && sim) {
     HX_TRY(launch_table(b->lt_xfer[2], s));
@@ -809,10 +804,8 @@ extern "C" int hx_batch_launch_phase(hx_batch* b, int phase, void* stream) {
       if (rows != b->bwd_rows_captured) return fail(HX_ERR_STATE, "gradients bound after the last backward: call hx_batch_backward once first");
     }
   }
-  if (phase == PH_BWD && b->world && b->staged_bwd) {  // the staged backward's three kernels
-    HX_TRY(launch_table(b->lt_bwd[0], (hipStream_t)stream));
-    HX_TRY(launch_table(b->lt_bwd[1], (hipStream_t)stream));
-  }
+  if (phase == PH_BWD && b->world && b->staged_bwd)  // the staged backward's forwarder sums first
+    HX_TRY(launch_table(b->lt_fwd_sum, (hipStream_t)stream));
   return launch_table(b->lt[phase], (hipStream_t)stream);
 }
 

@@ -87,43 +87,39 @@ __global__ void k_invert(const int32_t* __restrict__ map, int64_t n, int32_t* in
   }
 }
 
-// inv[map[i] - off] = base + i for a bijection onto [off, off + n) (other
-// targets are skipped and leave -1 for the range check).
-__global__ void k_invert_off(const int32_t* __restrict__ map, int64_t n, int64_t off, int64_t base, int32_t* inv) {
+// inv[map[i] - lo] = i for the n entries of an injective map (targets
+// outside [lo, lo + range) are skipped; untouched entries keep their fill).
+__global__ void k_invert_range(const int32_t* __restrict__ map, int64_t n, int64_t lo, int64_t range, int32_t* inv) {
   GRID_STRIDE(i, n) {
-    const int64_t t = (int64_t)map[i] - off;
-    if (t >= 0 && t < n) inv[t] = (int32_t)(base + i);
+    const int64_t t = (int64_t)map[i] - lo;
+    if (t >= 0 && t < range) inv[t] = (int32_t)i;
   }
 }
 
-__global__ void k_iota(int32_t* out, int64_t n) {
-  GRID_STRIDE(i, n) out[i] = (int32_t)i;
+// out[e] = b[off + a[e]] (composition of two maps).
+__global__ void k_compose(const int32_t* __restrict__ a, int64_t n, const int32_t* __restrict__ b, int64_t off,
+                          int32_t* out) {
+  GRID_STRIDE(e, n) out[e] = b[off + a[e]];
 }
 
-// own[k] = 1 for every stage-1 receive slot k (< R1_tot) that a halo entry
-// of its own rank reads.
-__global__ void k_mark_own(const int32_t* __restrict__ unpack, int64_t H, int64_t R1_tot, int32_t* own) {
-  GRID_STRIDE(i, H) {
-    const int32_t k = unpack[i];
-    if (k >= 0 && k < R1_tot) own[k] = 1;
-  }
+// Number of terms of every forwarder sum: the own-halo term when the slot's
+// own rank reads it (own[k] >= 0), plus its redistribution entries.
+__global__ void k_forward_lens(const int32_t* __restrict__ own, const int32_t* __restrict__ gp, int64_t n,
+                               int32_t* out) {
+  GRID_STRIDE(k, n) out[k] = (own[k] >= 0 ? 1 : 0) + gp[k + 1] - gp[k];
 }
 
 // Forwarder-sum CSR (staged backward): the terms of stage-1 receive slot k
-// are its own-halo term (row k of the gradient arena) when own[k], then the
-// redistribution entries that read k in ascending entry (rows S + e).
+// are its own halo's gradient row own[k] (when read), then the stage-2 send
+// slots e that forward it, in ascending e, as rows split + e.
 __global__ void k_forward_terms(const int32_t* __restrict__ own, const int32_t* __restrict__ gp,
                                 const int32_t* __restrict__ gperm, const int32_t* __restrict__ fptr, int64_t R1_tot,
-                                int64_t S, int32_t* fidx) {
+                                int64_t split, int32_t* fidx) {
   GRID_STRIDE(k, R1_tot) {
     int32_t pos = fptr[k];
-    if (own[k]) fidx[pos++] = (int32_t)k;
-    for (int32_t j = gp[k]; j < gp[k + 1]; ++j) fidx[pos++] = (int32_t)(S + gperm[j]);
+    if (own[k] >= 0) fidx[pos++] = own[k];
+    for (int32_t j = gp[k]; j < gp[k + 1]; ++j) fidx[pos++] = (int32_t)(split + gperm[j]);
   }
-}
-
-__global__ void k_add_i32(const int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t n, int32_t* out) {
-  GRID_STRIDE(i, n) out[i] = a[i] + b[i + 1] - b[i];
 }
 
 // Unpack map in world coordinates: slot u of rank r's [stage-1 | stage-2]
@@ -522,49 +518,54 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
     HX_TRY(dev_check_range(b->gidx_back.as<int32_t>(), b->E1_tot, b->H_tot, "reverse transfer", s));
   }
   // staged backward of a locality plan (the forward's stages reversed):
-  //   reverse unpack   G[unpack[i]] = g_halo[i]            (scatter, H rows)
-  //   reverse stage 2  G[S + e] = G[R1 + inv2[e]]          (transport)
-  //   forwarder sums   gR1[k] = sum of G[f_idx[f_ptr[k] ..]] (own term, then entries)
-  //   reverse stage 1  g_send[e] = gR1[inv1[e]]            (transport)
-  //   owner sums       g_x = pack transpose over g_send    (as the plain world)
-  // with G = [stage-1 recv | stage-2 recv | stage-2 send] gradient rows.
+  //   reverse unpack   a relabelling: the gradient of receive slot k is the
+  //                    halo gradient row that read it (inv_unpack[k])
+  //   reverse stage 2  g_s2[e] = g_halo[inv_unpack[R1 + inv2[e]]]   (transport)
+  //   forwarder sums   g_r1[k] = g_halo[own row of k] (when read), then
+  //                    g_s2[e] for the entries e forwarding k, ascending
+  //   reverse stage 1  g_send[e] = g_r1[inv1[e]]                     (transport)
+  //   owner sums       g_x = pack transpose over g_send (as the plain world)
   if ((flags & HX_WORLD_STAGED_BACKWARD) && !b->unpack_identity) {
     b->staged_bwd = true;
     const int64_t S = b->R1_tot + b->R2_tot;
     if (b->E1_tot != b->R1_tot || b->E2_tot != b->R2_tot)
       return fail(HX_ERR_ARG, "plan: sends and receives of a stage differ in size");
+    if (b->H_tot + b->E2_tot >= INT32_MAX) return fail(HX_ERR_UNSUPPORTED, "halo + stage-2 rows beyond 2^31");
+    DevMem inv_unpack, inv2, gp, gperm, lens;
+    HX_TRY(inv_unpack.alloc((size_t)std::max<int64_t>(S, 1) * 4));
+    HX_TRY(inv2.alloc((size_t)std::max<int64_t>(b->E2_tot, 1) * 4));
     HX_TRY(b->gidx_back.alloc((size_t)b->E1_tot * 4));
     HX_TRY(b->gidx_back2.alloc((size_t)b->E2_tot * 4));
-    HX_TRY(b->bwd_iota.alloc((size_t)(b->H_tot + 1) * 4));
+    hipLaunchKernelGGL(k_fill_neg, dim3(blocks_for(S + 1)), dim3(TB), 0, s, inv_unpack.as<int32_t>(), S);
+    if (b->H_tot)
+      hipLaunchKernelGGL(k_invert_range, dim3(blocks_for(b->H_tot)), dim3(TB), 0, s, b->gidx_unpack.as<int32_t>(),
+                         b->H_tot, (int64_t)0, S, inv_unpack.as<int32_t>());
     if (b->E1_tot) {
       hipLaunchKernelGGL(k_fill_neg, dim3(blocks_for(b->E1_tot)), dim3(TB), 0, s, b->gidx_back.as<int32_t>(), b->E1_tot);
-      hipLaunchKernelGGL(k_invert_off, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, b->gidx_x1.as<int32_t>(), b->R1_tot,
-                         (int64_t)0, (int64_t)0, b->gidx_back.as<int32_t>());
+      hipLaunchKernelGGL(k_invert_range, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, b->gidx_x1.as<int32_t>(),
+                         b->R1_tot, (int64_t)0, b->E1_tot, b->gidx_back.as<int32_t>());
     }
     if (b->E2_tot) {
-      hipLaunchKernelGGL(k_fill_neg, dim3(blocks_for(b->E2_tot)), dim3(TB), 0, s, b->gidx_back2.as<int32_t>(),
-                         b->E2_tot);
-      hipLaunchKernelGGL(k_invert_off, dim3(blocks_for(b->R2_tot)), dim3(TB), 0, s, b->gidx_x2.as<int32_t>(),
-                         b->R2_tot, b->E1_tot, b->R1_tot, b->gidx_back2.as<int32_t>());
+      hipLaunchKernelGGL(k_fill_neg, dim3(blocks_for(b->E2_tot)), dim3(TB), 0, s, inv2.as<int32_t>(), b->E2_tot);
+      hipLaunchKernelGGL(k_invert_range, dim3(blocks_for(b->R2_tot)), dim3(TB), 0, s, b->gidx_x2.as<int32_t>(),
+                         b->R2_tot, b->E1_tot, b->E2_tot, inv2.as<int32_t>());
     }
-    hipLaunchKernelGGL(k_iota, dim3(blocks_for(b->H_tot + 1)), dim3(TB), 0, s, b->bwd_iota.as<int32_t>(), b->H_tot + 1);
-    // forwarder-sum CSR
-    DevMem own, gp, gperm, lens;
-    HX_TRY(own.alloc((size_t)std::max<int64_t>(b->R1_tot, 1) * 4));
+    HX_HIP(hipGetLastError());
+    HX_TRY(dev_check_range(inv2.as<int32_t>(), b->E2_tot, b->R2_tot, "reverse stage-2 transfer", s));
+    if (b->E2_tot)
+      hipLaunchKernelGGL(k_compose, dim3(blocks_for(b->E2_tot)), dim3(TB), 0, s, inv2.as<int32_t>(), b->E2_tot,
+                         inv_unpack.as<int32_t>(), b->R1_tot, b->gidx_back2.as<int32_t>());
+    HX_HIP(hipGetLastError());
+    // forwarder-sum CSR; own rows are inv_unpack over the stage-1 slots
     HX_TRY(gp.alloc((size_t)(b->R1_tot + 1) * 4));
     HX_TRY(gperm.alloc((size_t)std::max<int64_t>(b->E2_tot, 1) * 4));
     HX_TRY(lens.alloc((size_t)(b->R1_tot + 1) * 4));
     HX_TRY(b->fwd_ptr.alloc((size_t)(b->R1_tot + 1) * 4));
-    hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(b->R1_tot + 1)), dim3(TB), 0, s, own.as<int32_t>(), b->R1_tot);
-    if (b->H_tot)
-      hipLaunchKernelGGL(k_mark_own, dim3(blocks_for(b->H_tot)), dim3(TB), 0, s, b->gidx_unpack.as<int32_t>(), b->H_tot,
-                         b->R1_tot, own.as<int32_t>());
-    HX_HIP(hipGetLastError());
     HX_TRY(dev_group_by_key(b->gidx_redist.as<int32_t>(), b->E2_tot, b->R1_tot, gp.as<int32_t>(), gperm.as<int32_t>(),
                             s));
     if (b->R1_tot)
-      hipLaunchKernelGGL(k_add_i32, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, own.as<int32_t>(), gp.as<int32_t>(),
-                         b->R1_tot, lens.as<int32_t>());
+      hipLaunchKernelGGL(k_forward_lens, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, inv_unpack.as<int32_t>(),
+                         gp.as<int32_t>(), b->R1_tot, lens.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(dev_exclusive_scan_i32(lens.as<int32_t>(), b->fwd_ptr.as<int32_t>(), b->R1_tot, s));
     int32_t nterms = 0;
@@ -572,14 +573,14 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
     b->fwd_terms = nterms;
     HX_TRY(b->fwd_idx.alloc((size_t)std::max<int32_t>(nterms, 1) * 4));
     if (b->R1_tot)
-      hipLaunchKernelGGL(k_forward_terms, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, own.as<int32_t>(),
-                         gp.as<int32_t>(), gperm.as<int32_t>(), b->fwd_ptr.as<int32_t>(), b->R1_tot, S,
+      hipLaunchKernelGGL(k_forward_terms, dim3(blocks_for(b->R1_tot)), dim3(TB), 0, s, inv_unpack.as<int32_t>(),
+                         gp.as<int32_t>(), gperm.as<int32_t>(), b->fwd_ptr.as<int32_t>(), b->R1_tot, b->H_tot,
                          b->fwd_idx.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_HIP(hipDeviceSynchronize());
     HX_TRY(dev_check_range(b->gidx_back.as<int32_t>(), b->E1_tot, b->R1_tot, "reverse stage-1 transfer", s));
-    HX_TRY(dev_check_range(b->gidx_back2.as<int32_t>(), b->E2_tot, S, "reverse stage-2 transfer", s));
-    HX_TRY(dev_check_range(b->fwd_idx.as<int32_t>(), nterms, S + b->E2_tot, "forwarder sums", s));
+    HX_TRY(dev_check_range(b->gidx_back2.as<int32_t>(), b->E2_tot, b->H_tot, "reverse stage-2 transfer", s));
+    HX_TRY(dev_check_range(b->fwd_idx.as<int32_t>(), nterms, b->H_tot + b->E2_tot, "forwarder sums", s));
   }
   // algorithmic bytes per phase
   {
@@ -591,9 +592,8 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
     b->bytes[PH_REDIST] = (b->E2_tot + U2) * rbi + 4 * b->E2_tot;
     b->bytes[PH_UNPACK] = 2 * b->H_tot * rbi + (b->unpack_identity ? 0 : 4 * b->H_tot);
     b->bytes[PH_BWD] = (b->H_tot + b->n) * rbi + 4 * (b->H_tot + b->n + 1);
-    if (b->staged_bwd)  // reverse unpack + forwarder sums + owner sums
-      b->bytes[PH_BWD] = (2 * b->H_tot * rbi + 4 * (2 * b->H_tot + 1)) +
-                         ((b->fwd_terms + b->R1_tot) * rbi + 4 * (b->fwd_terms + b->R1_tot + 1)) +
+    if (b->staged_bwd)  // forwarder sums + owner sums
+      b->bytes[PH_BWD] = ((b->fwd_terms + b->R1_tot) * rbi + 4 * (b->fwd_terms + b->R1_tot + 1)) +
                          ((b->E1_tot + b->n) * rbi + 4 * (b->E1_tot + b->n + 1));
   }
   HX_TRY(batch_init_scheds(b.get(), sched));
