@@ -84,11 +84,14 @@ typedef struct {
                          0 = default (push for rows of 64 bytes or more,
                          else pull) */
   int lds_window;     /* gathers: 1 = a job whose indices stay inside a known
-                         window of source rows (a rank's owned rows, its
-                         stage-1 receive arena) copies that window into LDS
-                         (when it fits in 80 KiB) and gathers from LDS;
-                         2 = gather from global memory; 0 = default (1 for
-                         rows of 16 bytes or less, else 2) */
+                         window of source rows (the pack: the rank's own
+                         rows; the redistribution: its stage-1 receive
+                         arena; a world's unpack: its stage-2 receive arena)
+                         copies that window into LDS (when it fits in 80 KiB
+                         and every index is inside it, checked on the device
+                         when the launch table is built) and gathers from
+                         LDS; 2 = gather from global memory; 0 = default (1
+                         for rows of 16 bytes or less, else 2) */
 } hx_sched;
 
 /* ---------------------------------------------------------------------------
@@ -298,19 +301,20 @@ int hx_batch_launch_phase(hx_batch* b, int phase, void* stream);
 int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out);
 /* World arenas: which = HX_ARENA_SEND / HX_ARENA_RECV, all ranks concatenated
  * as [stage-1 part of every rank | stage-2 part of every rank].
- * which = HX_ARENA_GRAD_SEND (plain worlds, after hx_batch_bind_grad): the
- * gradient slots of every rank's stage-1 send arena, laid out as the send
- * arena's stage-1 part.  The world backward of a plain plan sums these slots;
- * with HX_WORLD_SIM_TRANSFER the library fills them from g_halo_all (the
- * reverse transfer), otherwise the caller's transport must fill them before
- * hx_batch_backward.  Locality worlds read g_halo_all directly.
+ * which = HX_ARENA_GRAD_SEND (plain or staged-backward worlds, after
+ * hx_batch_bind_grad): the gradient slots of every rank's stage-1 send arena,
+ * laid out as the send arena's stage-1 part.  The world backward sums these
+ * slots per owned row; with HX_WORLD_SIM_TRANSFER the library fills them
+ * (the reverse transfer), otherwise the caller's transport must.  Locality
+ * worlds without the staged backward read g_halo_all directly.
  * hx_batch_arena_offset gives the first row of a rank's stage-1 part
  * (which = HX_ARENA_SEND / HX_ARENA_RECV) or stage-2 part (which | 2);
  * rank = nranks gives the end of the part. */
 int hx_batch_arena(hx_batch* b, int which, void** dev_ptr, int64_t* rows);
 int hx_batch_arena_offset(hx_batch* b, int which, int rank, int64_t* row_offset);
 /* Algorithmic bytes moved per phase launch (phase as in hx_batch_get_sched):
- * each read of a distinct source row, each output row written, each index. */
+ * each read of a distinct source row, each output row written, each index
+ * (phase 3 of a staged locality world: forwarder sums + owner sums). */
 int hx_batch_bytes(const hx_batch* b, int phase, int64_t* bytes);
 int hx_batch_free(hx_batch** b);
 

@@ -612,7 +612,8 @@ extern "C" int hx_batch_arena(hx_batch* b, int which, void** dev_ptr, int64_t* r
     *dev_ptr = b->recv_all.p;
     *rows = b->R1_tot + b->R2_tot;
   } else if (which == HX_ARENA_GRAD_SEND) {
-    if (!b->unpack_identity) return fail(HX_ERR_ARG, "locality worlds have no gradient send arena");
+    if (!b->unpack_identity && !b->staged_bwd)
+      return fail(HX_ERR_ARG, "locality worlds without the staged backward have no gradient send arena");
     if (!b->g_out) return fail(HX_ERR_STATE, "no gradient buffers bound");
     *dev_ptr = b->g_send_all.p;
     *rows = b->E1_tot;
