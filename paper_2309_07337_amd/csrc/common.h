@@ -84,6 +84,10 @@ struct SegSumJob {
   int64_t nrows;
   const char* in2 = nullptr;
   int32_t split = INT32_MAX;
+  // segmented sums: terms [win_lo, win_lo + win_rows) (all in one input) may
+  // be staged in LDS (win_rows = 0: none)
+  int64_t win_lo = 0;
+  int64_t win_rows = 0;
 };
 
 // Gather: pull rows through an index (GatherJob).  Segsum: fixed-order sum
@@ -119,6 +123,9 @@ constexpr int kSegValueBytes = 32768;
 // Largest source window a gather stages in LDS (larger ones read global
 // memory): two such workgroups fit in the 160 KiB of a gfx950 CU.
 constexpr int kWinBytes = 80 << 10;
+// Same for a segmented sum's term window (its workgroups also hold about
+// 6.5 KiB of staged pointers and indices).
+constexpr int kSegWinBytes = 72 << 10;
 Sched resolve_sched(const hx_sched* s, int kind, int row_bytes);
 hx_sched to_public(const Sched& s);
 

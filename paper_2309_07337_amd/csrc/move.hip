@@ -149,7 +149,34 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
 int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
                        LaunchTable* t, int tag) {
   t->tag = tag;
-  return build_table(jobs, KIND_SEGSUM, dtype, row_bytes, s, t, align_of(jobs, row_bytes));
+  // term windows: kept where the schedule asks for them, they fit, and they
+  // lie inside one of the two inputs
+  // (all jobs or none: a job without a window would run the windowed form's
+  // row-parallel loop from global memory, slower than the plain form)
+  std::vector<SegSumJob> w(jobs);
+  const int64_t cap = std::min<int64_t>(kSegWinBytes, device_lds_per_block() - (8 << 10));
+  int64_t win_bytes = 0;
+  bool all = s.lds_window != 0;
+  for (const auto& j : w) {
+    if (j.nrows <= 0) continue;
+    const int64_t bytes = j.win_rows * (int64_t)row_bytes;
+    const int64_t hi = j.win_lo + j.win_rows;
+    const bool one_input = hi <= j.split || j.win_lo >= j.split;
+    if (j.win_rows <= 0 || j.win_lo < 0 || bytes > cap || !one_input) all = false;
+    else win_bytes = std::max(win_bytes, bytes);
+  }
+  if (!all) {
+    win_bytes = 0;
+    for (auto& j : w) j.win_lo = j.win_rows = 0;
+  }
+  uintptr_t a = align_of(w, row_bytes);
+  for (const auto& j : w)
+    if (j.win_rows > 0 && j.nrows > 0)
+      a |= (uintptr_t)(j.win_lo < j.split ? j.in + j.win_lo * (int64_t)row_bytes
+                                           : j.in2 + (j.win_lo - j.split) * (int64_t)row_bytes);
+  HX_TRY(build_table(w, KIND_SEGSUM, dtype, row_bytes, s, t, a));
+  t->win_bytes = t->ntiles > 0 ? (int)win_bytes : 0;
+  return HX_SUCCESS;
 }
 
 int build_scatter_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,

@@ -598,6 +598,120 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Segmented sum over a term window (short rows): a job whose terms mostly lie
+// in [win_lo, win_lo + win_rows) of its term space (a rank's own send or
+// forwarding slots, all inside one of the two inputs) copies those rows into
+// dynamic LDS once per job; each row then adds its terms in order, reading
+// in-window terms from LDS and the others (own-halo terms of a forwarder)
+// from global memory.  Pointers and entry indices are staged per tile (tiles
+// of at most 128 rows and 1536 entries; others read them from global
+// memory).  No term staging buffer, so two such workgroups fit per CU.
+// ---------------------------------------------------------------------------
+template <class T, int VB, int NV, int LPR, int U, bool NT>
+__device__ __forceinline__ void segsum_win_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
+                                                int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
+  using V = typename NumVec<T, VB>::type;
+  static_assert(NV > 0, "windowed segmented sums use fixed row shapes");
+  constexpr int NVPL = (NV + LPR - 1) / LPR;
+  (void)nv_rt;
+  const int lane_v = threadIdx.x % LPR;
+  const int rsub = threadIdx.x / LPR;
+  const int rows_per_pass = blockDim.x / LPR;
+  constexpr int WROWS = 128, WENTRIES = 1536;  // smaller staging: the window takes the LDS
+  __shared__ int32_t s_ptr[WROWS + 1];
+  __shared__ int32_t s_idx[WENTRIES];
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  V* __restrict__ s_win = reinterpret_cast<V*>(s_dyn);
+  const bool stage_ptr = tile_rows <= WROWS;
+  constexpr size_t rb = (size_t)NV * VB;
+  int64_t t0, t1;
+  tile_range(ntiles, &t0, &t1);
+  if (t0 >= t1) return;
+  int j = find_job(ts, njobs, t0);
+  int staged = -1;
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= ts[j + 1]) ++j;
+    const char* __restrict__ in = jobs[j].in;
+    const int32_t split = jobs[j].split;
+    const char* __restrict__ in2 = jobs[j].in2;
+    char* __restrict__ out = jobs[j].out;
+    const int32_t* __restrict__ ptr = jobs[j].ptr;
+    const int32_t* __restrict__ idx = jobs[j].idx;
+    const int64_t nrows = jobs[j].nrows;
+    const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
+    const int32_t win_lo = (int32_t)jobs[j].win_lo;
+    const int32_t win_rows = (int32_t)jobs[j].win_rows;
+    if (win_rows > 0 && staged != j) {
+      __syncthreads();  // every lane is done with the previous window
+      const V* __restrict__ wp = reinterpret_cast<const V*>(term_row(in, in2, split, win_lo, rb));
+      const int nvec = win_rows * NV;
+      constexpr int UW = 8;
+      for (int i0 = threadIdx.x; i0 < nvec; i0 += blockDim.x * UW) {
+        V w[UW];
+#pragma unroll
+        for (int u = 0; u < UW; ++u) {
+          const int i = i0 + u * blockDim.x;
+          if (i < nvec) w[u] = wp[i];
+        }
+#pragma unroll
+        for (int u = 0; u < UW; ++u) {
+          const int i = i0 + u * blockDim.x;
+          if (i < nvec) s_win[i] = w[u];
+        }
+      }
+      staged = j;
+    }
+    int32_t P0 = 0;
+    bool stage_idx = false;
+    const int nt = (int)(r1 - r0);
+    if (stage_ptr) {
+      for (int i = threadIdx.x; i <= nt; i += blockDim.x) s_ptr[i] = ptr[r0 + i];
+      __syncthreads();
+      P0 = s_ptr[0];
+      const int32_t ne = s_ptr[nt] - P0;
+      stage_idx = ne <= WENTRIES;
+      if (stage_idx)
+        for (int i = threadIdx.x; i < ne; i += blockDim.x) s_idx[i] = ldv<int32_t, NT>(idx + P0 + i);
+    }
+    __syncthreads();  // staged window, pointers and indices visible to all lanes
+    for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = base + (int64_t)u * rows_per_pass;
+        if (r >= r1) break;
+        const int32_t a = stage_ptr ? s_ptr[r - r0] : ptr[r];
+        const int32_t len = (stage_ptr ? s_ptr[r - r0 + 1] : ptr[r + 1]) - a;
+        V acc[NVPL];
+#pragma unroll
+        for (int k = 0; k < NVPL; ++k) acc[k] = (V)(T)0;
+        for (int32_t d = 0; d < len; ++d) {
+          const int32_t tm = stage_idx ? s_idx[a + d - P0] : ldv<int32_t, NT>(idx + a + d);
+          const uint32_t wr = (uint32_t)(tm - win_lo);
+#pragma unroll
+          for (int k = 0; k < NVPL; ++k) {
+            const int vi = lane_v + k * LPR;
+            if (NV % LPR == 0 || vi < NV) {
+              V v;
+              if (wr < (uint32_t)win_rows) v = s_win[(int64_t)wr * NV + vi];
+              else v = reinterpret_cast<const V*>(term_row(in, in2, split, tm, rb))[vi];
+              acc[k] = d == 0 ? v : acc[k] + v;
+            }
+          }
+        }
+        V* dp = reinterpret_cast<V*>(out + r * (int64_t)rb);
+#pragma unroll
+        for (int k = 0; k < NVPL; ++k) {
+          const int vi = lane_v + k * LPR;
+          if (NV % LPR == 0 || vi < NV) stv<V, NT>(dp + vi, acc[k]);
+        }
+      }
+    }
+    __syncthreads();  // the next tile overwrites the staged pointers and indices
+  }
+}
+
 }  // namespace kern
 
 // Launchers implemented in the move_*.hip translation units.

@@ -1,6 +1,7 @@
 // Fixed-order segmented sums, instantiated for FP32 and FP64 rows: the owner
 // sums (the backward of the pack and of the exchange) and the staged
-// backward's forwarder sums.  One symbol per step, same body.
+// backward's forwarder sums.  One symbol per step (and a *_win form with an
+// LDS term window), same bodies.
 #include "move_launch.h"
 
 namespace hx {
@@ -14,6 +15,12 @@ namespace {
            int64_t ntiles, int tile_rows, int nv_rt) {                                               \
     segsum_body<T, VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt);                   \
   }                                                                                                  \
+  template <class T, int VB, int NV, int LPR, int U, bool NT>                                        \
+  __global__ void __launch_bounds__(512)                                                             \
+      NAME##_win(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs,      \
+                 int64_t ntiles, int tile_rows, int nv_rt) {                                         \
+    segsum_win_body<T, VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt);               \
+  }                                                                                                  \
   template <class T>                                                                                 \
   struct NAME##_go {                                                                                 \
     template <int VB, int NV, int LPR, int U, bool NT>                                               \
@@ -21,6 +28,15 @@ namespace {
       if constexpr ((size_t)VB < sizeof(T)) {                                                        \
         (void)t; (void)s; (void)nv; /* excluded when the table is built */                           \
       } else {                                                                                       \
+        if constexpr (NV > 0 && NV * VB <= 64) { /* term windows pay off for short rows only */    \
+          if (t.win_bytes > 0) {                                                                     \
+            hipLaunchKernelGGL((NAME##_win<T, VB, NV, LPR, U, NT>), dim3(t.grid),                    \
+                               dim3(t.sched.block_threads), (unsigned)t.win_bytes, s,                \
+                               t.jobs.as<SegSumJob>(), t.tile_start.as<int64_t>(), t.njobs,          \
+                               t.ntiles, t.sched.tile_rows, nv);                                     \
+            return;                                                                                  \
+          }                                                                                          \
+        }                                                                                            \
         hipLaunchKernelGGL((NAME<T, VB, NV, LPR, U, NT>), dim3(t.grid), dim3(t.sched.block_threads), \
                            0, s, t.jobs.as<SegSumJob>(), t.tile_start.as<int64_t>(), t.njobs,        \
                            t.ntiles, t.sched.tile_rows, nv);                                         \

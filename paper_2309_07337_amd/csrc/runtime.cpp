@@ -118,8 +118,8 @@ Sched default_sched(int kind, int row_bytes) {
   // writes run as fast as scattered reads, and the push form reads each
   // source row once instead of once per slot); short rows: pull
   s.push_pack = kind == KIND_GATHER && row_bytes >= 64 ? 1 : 0;
-  // short rows: gathers read their jobs' source windows from LDS
-  s.lds_window = kind == KIND_GATHER && row_bytes <= 16 ? 1 : 0;
+  // short rows: gathers and segmented sums read their jobs' windows from LDS
+  s.lds_window = row_bytes <= 16 ? 1 : 0;
   return s;
 }
 
@@ -267,9 +267,11 @@ static int req_phase_jobs(const hx_req* r, int phase, const Sched& sc, std::vect
       break;
     }
     case PH_BWD: {
-      if (r->g_x && (r->g_send || r->E1 == 0))
-        s->push_back(SegSumJob{r->g_send, r->g_x, r->bt_ptr.as<int32_t>(), r->bt_perm.as<int32_t>(),
-                               r->n_local});
+      if (r->g_x && (r->g_send || r->E1 == 0)) {
+        SegSumJob jb{r->g_send, r->g_x, r->bt_ptr.as<int32_t>(), r->bt_perm.as<int32_t>(), r->n_local};
+        jb.win_rows = r->E1;  // the terms are the request's own send-slot gradients
+        s->push_back(jb);
+      }
       break;
     }
     default:
@@ -735,10 +737,19 @@ extern "C" int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out) {
     HX_TRY(b->g_s2.alloc((size_t)b->E2_tot * b->row_bytes));
     HX_TRY(b->g_r1.alloc((size_t)b->R1_tot * b->row_bytes));
     HX_TRY(b->g_send_all.alloc((size_t)b->E1_tot * b->row_bytes));
-    SegSumJob fj{b->g_in, b->g_r1.as<char>(), b->fwd_ptr.as<int32_t>(), b->fwd_idx.as<int32_t>(), b->R1_tot};
-    fj.in2 = b->g_s2.as<char>();
-    fj.split = (int32_t)b->H_tot;
-    HX_TRY(build_segsum_table({fj}, b->dtype, rbi, default_sched(KIND_SEGSUM, rbi), &b->lt_fwd_sum, TAG_FWD_SUM));
+    // one job per forwarder: its terms are mostly its own stage-2 slots (the window)
+    std::vector<SegSumJob> fjs;
+    for (int q = 0; q < b->R; ++q) {
+      const int64_t k0 = b->r1_off[q];
+      SegSumJob fj{b->g_in, b->g_r1.as<char>() + k0 * (int64_t)b->row_bytes, b->fwd_ptr.as<int32_t>() + k0,
+                   b->fwd_idx.as<int32_t>(), b->r1_off[q + 1] - k0};
+      fj.in2 = b->g_s2.as<char>();
+      fj.split = (int32_t)b->H_tot;
+      fj.win_lo = b->H_tot + b->s2_off[q];
+      fj.win_rows = b->s2_off[q + 1] - b->s2_off[q];
+      fjs.push_back(fj);
+    }
+    HX_TRY(build_segsum_table(fjs, b->dtype, rbi, default_sched(KIND_SEGSUM, rbi), &b->lt_fwd_sum, TAG_FWD_SUM));
     std::vector<GatherJob> x2{GatherJob{b->g_in, b->g_s2.as<char>(), b->gidx_back2.as<int32_t>(), b->E2_tot}};
     HX_TRY(build_gather_table(x2, b->dtype, rbi, gsc, &b->lt_xfer[3]));
     std::vector<GatherJob> x1{GatherJob{b->g_r1.as<char>(), b->g_send_all.as<char>(), b->gidx_back.as<int32_t>(),
@@ -885,12 +896,12 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
           for (int push : {0, 1})
             for (int win : {0, 1}) {
               if (push && ph != PH_PACK) continue;
-              if (win && (ph == PH_BWD || push)) continue;
+              if (win && push) continue;
               Sched c = s0;
               c.tile_rows = std::max(16, base * tf / 8);
               c.unroll = u;
               c.push_pack = ph == PH_PACK ? push : s0.push_pack;
-              c.lds_window = ph == PH_BWD ? s0.lds_window : win;
+              c.lds_window = win;
               c.per_neighbor = 0;
               consider(c);
             }

@@ -252,13 +252,22 @@ int world_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
       const char* in = local ? b->g_send_all.as<char>() : b->g_in;
       const int32_t* ptr = local ? b->wp_ptr.as<int32_t>() : b->wb_ptr.as<int32_t>();
       const int32_t* idx = local ? b->wp_idx.as<int32_t>() : b->wb_idx.as<int32_t>();
-      if (merged) {
+      if (merged && !(local && sc.lds_window)) {
         s->push_back({SegSumJob{in, b->g_out, ptr, idx, b->n}});
       } else {
+        // one job per rank; its terms are its own send slots (the window)
+        std::vector<SegSumJob> v;
         for (int r = 0; r < b->R; ++r) {
           const int64_t r0 = b->row_starts[r];
-          s->push_back({SegSumJob{in, b->g_out + r0 * rb, ptr + r0, idx, b->row_starts[r + 1] - r0}});
+          SegSumJob jb{in, b->g_out + r0 * rb, ptr + r0, idx, b->row_starts[r + 1] - r0};
+          if (local) {
+            jb.win_lo = b->s1_off[r];
+            jb.win_rows = b->s1_off[r + 1] - b->s1_off[r];
+          }
+          v.push_back(jb);
         }
+        if (merged) s->push_back(v);
+        else for (auto& x : v) s->push_back({x});
       }
       break;
     }
