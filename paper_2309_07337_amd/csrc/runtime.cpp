@@ -554,6 +554,26 @@ int hx::batch_build_plain(hx_batch* b, int phase) {
 
 // (Re)builds the batched tables for the current schedules and captures the
 // start / wait / backward graphs.
+// Forwarder sums of a staged locality world (bound gradients), one job per
+// forwarder: its terms are its own halo's rows and, mostly, its own stage-2
+// slots (the window).  Runs on the backward phase's schedule.
+static int build_fwd_sum_table(const hx_batch* b, const Sched& sc, LaunchTable* t) {
+  *t = LaunchTable();
+  if (!b->staged_bwd || !b->g_out) return HX_SUCCESS;
+  std::vector<SegSumJob> fjs;
+  for (int q = 0; q < b->R; ++q) {
+    const int64_t k0 = b->r1_off[q];
+    SegSumJob fj{b->g_in, b->g_r1.as<char>() + k0 * (int64_t)b->row_bytes, b->fwd_ptr.as<int32_t>() + k0,
+                 b->fwd_idx.as<int32_t>(), b->r1_off[q + 1] - k0};
+    fj.in2 = b->g_s2.as<char>();
+    fj.split = (int32_t)b->H_tot;
+    fj.win_lo = b->H_tot + b->s2_off[q];
+    fj.win_rows = b->s2_off[q + 1] - b->s2_off[q];
+    fjs.push_back(fj);
+  }
+  return build_segsum_table(fjs, b->dtype, (int)b->row_bytes, sc, t, TAG_FWD_SUM);
+}
+
 int hx::batch_prepare(hx_batch* b) {
   batch_destroy_graphs(b);
   if (!b->world) {
@@ -561,6 +581,7 @@ int hx::batch_prepare(hx_batch* b) {
     for (hx_req* r : b->members) b->bwd_rows_captured += (r->g_x ? r->n_local : 0);
   }
   for (int ph = 0; ph < 4; ++ph) HX_TRY(batch_build_table(b, ph, b->sched[ph], &b->lt[ph]));
+  HX_TRY(build_fwd_sum_table(b, b->sched[PH_BWD], &b->lt_fwd_sum));
   if (!b->cap_stream) HX_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   HX_TRY(capture_graph(b->cap_stream, [&](hipStream_t s) { return batch_run_start(b, s); }, &b->graph[0],
                        &b->has_graph[0]));
@@ -737,19 +758,6 @@ extern "C" int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out) {
     HX_TRY(b->g_s2.alloc((size_t)b->E2_tot * b->row_bytes));
     HX_TRY(b->g_r1.alloc((size_t)b->R1_tot * b->row_bytes));
     HX_TRY(b->g_send_all.alloc((size_t)b->E1_tot * b->row_bytes));
-    // one job per forwarder: its terms are mostly its own stage-2 slots (the window)
-    std::vector<SegSumJob> fjs;
-    for (int q = 0; q < b->R; ++q) {
-      const int64_t k0 = b->r1_off[q];
-      SegSumJob fj{b->g_in, b->g_r1.as<char>() + k0 * (int64_t)b->row_bytes, b->fwd_ptr.as<int32_t>() + k0,
-                   b->fwd_idx.as<int32_t>(), b->r1_off[q + 1] - k0};
-      fj.in2 = b->g_s2.as<char>();
-      fj.split = (int32_t)b->H_tot;
-      fj.win_lo = b->H_tot + b->s2_off[q];
-      fj.win_rows = b->s2_off[q + 1] - b->s2_off[q];
-      fjs.push_back(fj);
-    }
-    HX_TRY(build_segsum_table(fjs, b->dtype, rbi, default_sched(KIND_SEGSUM, rbi), &b->lt_fwd_sum, TAG_FWD_SUM));
     std::vector<GatherJob> x2{GatherJob{b->g_in, b->g_s2.as<char>(), b->gidx_back2.as<int32_t>(), b->E2_tot}};
     HX_TRY(build_gather_table(x2, b->dtype, rbi, gsc, &b->lt_xfer[3]));
     std::vector<GatherJob> x1{GatherJob{b->g_r1.as<char>(), b->g_send_all.as<char>(), b->gidx_back.as<int32_t>(),
@@ -876,6 +884,13 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
       if (rc != HX_SUCCESS) return;
       float ms = 0;
       rc = time_table(t, s, e0, e1, 3, &ms);
+      if (rc == HX_SUCCESS && ph == PH_BWD && b->staged_bwd) {  // forwarder sums share the schedule
+        LaunchTable tf;
+        float msf = 0;
+        rc = build_fwd_sum_table(b, c, &tf);
+        if (rc == HX_SUCCESS) rc = time_table(tf, s, e0, e1, 3, &msf);
+        ms += msf;
+      }
       if (log)
         std::fprintf(stderr, "hx tune phase %d: tile %d bt %d bpc %d nt %d unroll %d push %d win %d: %.4f ms\n", ph,
                      c.tile_rows, c.block_threads, c.blocks_per_cu, c.nontemporal, c.unroll, c.push_pack,
