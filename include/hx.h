@@ -234,6 +234,23 @@ int hx_req_arena(hx_req* req, int which, void** dev_ptr, int64_t* rows);
  * -0.0 stays -0.0), rows never packed get +0.0.  g_send device [E1, ncols],
  * g_x device [n_local, ncols]; bound persistently. */
 int hx_req_bind_grad(hx_req* req, const void* g_send, void* g_x);
+/* Partition-ready pack (the GPU half of partitioned, early-bird sends):
+ * hx_req_enable_ready allocates one 64-bit completion counter per stage-1
+ * message (in the order of the request's send list), zeroed, owned by the
+ * request, and returns their device address.  From then on the pack runs in
+ * the pull form with one job per message, and after each tile the rows it
+ * wrote are added to its message's counter once they are visible
+ * device-wide (release fence, then atomic add).  After the k-th pack since
+ * enabling (hx_start, a batch Start, or hx_batch_launch_phase of the pack;
+ * the tuner's trial launches do not count), counter[m] reaches
+ * k * sendcounts[m] exactly when message m of that pack is complete, so a
+ * transport (a kernel on another stream, a copy engine) may send each
+ * message as soon as its counter reaches the target (with an acquire load)
+ * instead of waiting for the whole pack.  Counters only grow (nothing to
+ * reset inside captured graphs).  Batches take the mode from their members
+ * at hx_batch_init (their pack then runs in the pull form).  HX_ERR_STATE
+ * while the request is active. */
+int hx_req_enable_ready(hx_req* req, unsigned long long** dev_counters);
 int hx_backward(hx_req* req, void* stream);
 int hx_req_free(hx_req** req);
 

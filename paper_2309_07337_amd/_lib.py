@@ -36,7 +36,7 @@ EXPORTED = (
     "hx_topo_create", "hx_topo_free", "hx_neighbor_alltoallv_init",
     "hx_plan_from_csr", "hx_plan_from_halos", "hx_plan_free", "hx_plan_field_size",
     "hx_plan_field_copy", "hx_req_from_plan", "hx_start", "hx_wait", "hx_req_arena",
-    "hx_req_bind_grad", "hx_backward", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
+    "hx_req_bind_grad", "hx_req_enable_ready", "hx_backward", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
     "hx_batch_start", "hx_batch_wait", "hx_batch_start_plain", "hx_batch_wait_plain",
     "hx_batch_bind_grad", "hx_batch_backward", "hx_batch_backward_plain", "hx_batch_tune",
     "hx_batch_launch_phase", "hx_batch_get_sched", "hx_batch_arena", "hx_batch_arena_offset", "hx_batch_bytes",
@@ -105,6 +105,7 @@ def load() -> C.CDLL:
         "hx_batch_backward": (C.c_int, [VP, VP]),
         "hx_batch_backward_plain": (C.c_int, [VP, VP]),
         "hx_batch_tune": (C.c_int, [VP, VP]),
+        "hx_req_enable_ready": (C.c_int, [VP, PP]),
         "hx_batch_launch_phase": (C.c_int, [VP, C.c_int, VP]),
         "hx_batch_get_sched": (C.c_int, [VP, C.c_int, C.POINTER(hx_sched)]),
         "hx_batch_arena": (C.c_int, [VP, C.c_int, PP, I64P]),
@@ -297,6 +298,14 @@ def hx_req_bind_grad(req: Req, g_send, g_x) -> None:
     req._keep += [g_send, g_x]
 
 
+def hx_req_enable_ready(req: Req) -> int:
+    """Per-message completion counters of the pack (device address of
+    len(send list) uint64 counters owned by the request)."""
+    p = C.c_void_p()
+    _check(load().hx_req_enable_ready(req.ptr, C.byref(p)))
+    return p.value or 0
+
+
 def hx_backward(req: Req, stream=None) -> None:
     _check(load().hx_backward(req.ptr, _stream(stream)))
 
@@ -397,7 +406,7 @@ def device_view(ptr: int, rows: int, ncols: int, dtype):
     import torch
     if rows == 0 or not ptr:
         return torch.empty((rows, ncols), dtype=dtype, device="cuda")
-    typestr = {torch.float64: "<f8", torch.float32: "<f4", torch.int32: "<i4"}[dtype]
+    typestr = {torch.float64: "<f8", torch.float32: "<f4", torch.int32: "<i4", torch.int64: "<i8"}[dtype]
     return torch.as_tensor(_ArrayInterface(ptr, (rows, ncols), typestr), device="cuda")
 
 

@@ -72,6 +72,9 @@ struct GatherJob {
   int64_t nrows;
   int64_t win_lo = 0;
   int64_t win_rows = 0;
+  // when set: after each tile, the rows it wrote are added to *ready once
+  // they are visible device-wide (a message's completion counter)
+  unsigned long long* ready = nullptr;
 };
 // out[i, :] = in[idx[ptr[i]], :] + in[idx[ptr[i]+1], :] + ... (ascending,
 // first term first; empty -> +0) for i < nrows.  Terms t >= split come from

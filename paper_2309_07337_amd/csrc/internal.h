@@ -33,6 +33,7 @@ struct hx_req {
   bool active = false;
   bool tables_built = false;
   hx::LaunchTable lt[4];
+  hx::DevMem ready;  // per stage-1 message completion counters (uint64), when enabled
 };
 
 // Plan of a whole decomposition: per-rank arrays stored flat on the device,
@@ -68,6 +69,7 @@ struct hx_batch {
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   bool has_graph[3] = {false, false, false};
   bool active = false;
+  bool tuning = false;                      // hx_batch_tune running: candidates skip completion counters
   int64_t bytes[4] = {0, 0, 0, 0};
   int64_t bwd_rows_captured = 0;
   // world (all ranks of a plan over flat arrays)

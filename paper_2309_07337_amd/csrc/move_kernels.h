@@ -59,6 +59,19 @@ __device__ __forceinline__ void tile_range(int64_t ntiles, int64_t* t0, int64_t*
   *t1 = (int64_t)(L + 1) * ntiles / nb;
 }
 
+// Completion counter of a message (partition-ready pack): once every lane's
+// stores of the tile are done (workgroup barrier), one lane makes them
+// visible device-wide (release fence) and adds the tile's rows.  A reader
+// that sees the counter reach its target (acquire) sees the rows.
+__device__ __forceinline__ void signal_tile(unsigned long long* ready, int64_t rows) {
+  if (ready == nullptr) return;  // uniform: the whole tile belongs to one job
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(ready, (unsigned long long)rows);
+  }
+}
+
 // Largest j with ts[j] <= t (jobs with no tiles are skipped).
 __device__ __forceinline__ int find_job(const int64_t* __restrict__ ts, int njobs, int64_t t) {
   int lo = 0, hi = njobs - 1;
@@ -154,6 +167,7 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
             if (k < nvec) stv<V, NT>(dp + k, c[u]);
           }
         }
+        signal_tile(jobs[j].ready, r1 - r0);
         continue;
       }
     }
@@ -214,6 +228,7 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
         for (int vi = lane_v; vi < nv; vi += LPR) stv<V, NT>(dp + vi, sp[vi]);
       }
     }
+    signal_tile(jobs[j].ready, r1 - r0);
   }
 }
 

@@ -217,7 +217,10 @@ static int req_phase_jobs(const hx_req* r, int phase, const Sched& sc, std::vect
 int hx::build_phase_table(int phase, const Sched& sc, int dtype, int row_bytes, const std::vector<GatherJob>& g,
                           const std::vector<SegSumJob>& s, LaunchTable* t) {
   if (phase == PH_BWD) return build_segsum_table(s, dtype, row_bytes, sc, t);
-  if (phase == PH_PACK && sc.push_pack) return build_scatter_table(s, dtype, row_bytes, sc, t);
+  // (a request with completion counters packs in the pull form whatever the schedule)
+  if (phase == PH_PACK && sc.push_pack && g.empty()) return build_scatter_table(s, dtype, row_bytes, sc, t);
+  if (phase == PH_PACK && !g.empty() && !s.empty())
+    return fail(HX_ERR_STATE, "pack jobs of both forms in one launch");
   return build_gather_table(g, dtype, row_bytes, sc, t, phase);
 }
 
@@ -241,6 +244,22 @@ static int req_phase_jobs(const hx_req* r, int phase, const Sched& sc, std::vect
   const bool per_nbr = sc.per_neighbor != 0;
   switch (phase) {
     case PH_PACK: {
+      if (r->ready.p) {
+        // partition-ready pack: pull form, one job per message, each with its
+        // message's completion counter
+        auto* cnt = r->ready.as<unsigned long long>();
+        int64_t off = 0;
+        for (size_t m = 0; m < r->s1_counts.size(); ++m) {
+          const int64_t c = r->s1_counts[m];
+          if (c > 0) {
+            GatherJob j{r->x, r->send.as<char>() + off * (int64_t)rb, r->s1_idx.as<int32_t>() + off, c, 0, r->n_local};
+            j.ready = cnt + m;
+            g->push_back(j);
+          }
+          off += c;
+        }
+        break;
+      }
       if (sc.push_pack) {
         if (r->E1 > 0)
           s->push_back(SegSumJob{r->x, r->send.as<char>(), r->bt_ptr.as<int32_t>(), r->bt_perm.as<int32_t>(),
@@ -416,6 +435,19 @@ extern "C" int hx_req_arena(hx_req* r, int which, void** dev_ptr, int64_t* rows)
   return HX_SUCCESS;
 }
 
+extern "C" int hx_req_enable_ready(hx_req* r, unsigned long long** dev_counters) {
+  if (!r || !dev_counters) return fail(HX_ERR_ARG, "null argument");
+  if (r->active) return fail(HX_ERR_STATE, "request active");
+  if (!r->ready.p) {
+    const size_t n = std::max<size_t>(r->s1_counts.size(), 1);
+    HX_TRY(r->ready.alloc(n * sizeof(unsigned long long)));
+    HX_HIP(hipMemset(r->ready.p, 0, n * sizeof(unsigned long long)));
+    r->tables_built = false;  // the pack is rebuilt per message
+  }
+  *dev_counters = r->ready.as<unsigned long long>();
+  return HX_SUCCESS;
+}
+
 extern "C" int hx_req_bind_grad(hx_req* r, const void* g_send, void* g_x) {
   if (!r) return fail(HX_ERR_ARG, "null request");
   if ((r->E1 > 0 && !g_send) || (r->n_local > 0 && !g_x)) return fail(HX_ERR_ARG, "null gradient buffer");
@@ -513,6 +545,8 @@ int hx::batch_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool mer
     std::vector<GatherJob> gj;
     std::vector<SegSumJob> sj;
     HX_TRY(req_phase_jobs(r, phase, sc, &gj, &sj));
+    if (b->tuning)  // candidate launches of the tuner leave completion counters alone
+      for (auto& j : gj) j.ready = nullptr;
     g->push_back(gj);
     s->push_back(sj);
   }
@@ -652,6 +686,13 @@ static void cache_store(const std::string& key, const Sched& s) {
     << ' ' << s.per_neighbor << ' ' << s.unroll << ' ' << s.push_pack << ' ' << s.lds_window << '\n';
 }
 
+// Members with pack completion counters need the pull form of the pack.
+static bool batch_has_ready(const hx_batch* b) {
+  for (const hx_req* r : b->members)
+    if (r->ready.p) return true;
+  return false;
+}
+
 int hx::batch_init_scheds(hx_batch* b, const hx_sched* sched) {
   for (int ph = 0; ph < 4; ++ph) {
     const int kind = ph == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
@@ -662,6 +703,7 @@ int hx::batch_init_scheds(hx_batch* b, const hx_sched* sched) {
       b->sched[ph] = cache_lookup(cache_key(b, ph), &s) ? s : default_sched(kind, (int)b->row_bytes);
     }
   }
+  if (batch_has_ready(b)) b->sched[PH_PACK].push_pack = 0;
   return HX_SUCCESS;
 }
 
@@ -869,6 +911,11 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
   HX_HIP(hipEventCreate(&e0));
   HX_HIP(hipEventCreate(&e1));
   const bool log = std::getenv("HX_TUNE_LOG") != nullptr;  // every candidate's time on stderr
+  struct TuningFlag {
+    hx_batch* b;
+    ~TuningFlag() { b->tuning = false; }
+  } tuning_flag{b};
+  b->tuning = true;
   int rc = HX_SUCCESS;
   for (int ph = 0; ph < 4 && rc == HX_SUCCESS; ++ph) {
     if (b->lt[ph].empty()) continue;
@@ -910,7 +957,7 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
         for (int u : {1, 2, 4})
           for (int push : {0, 1})
             for (int win : {0, 1}) {
-              if (push && ph != PH_PACK) continue;
+              if (push && (ph != PH_PACK || batch_has_ready(b))) continue;
               if (win && push) continue;
               Sched c = s0;
               c.tile_rows = std::max(16, base * tf / 8);
@@ -948,6 +995,7 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  b->tuning = false;  // the tables kept for Start/Wait signal their counters again
   HX_TRY(rc);
   return batch_prepare(b);
 }

@@ -125,3 +125,50 @@ def test_misaligned_and_bad_arguments():
     with pytest.raises(P.HXError) as e:
         P.hx_neighbor_alltoallv_init(x, [2], [1], [0, 1], halo, [2], [0], topo)
     assert e.value.code == P.HX_ERR_ARG
+
+
+def counters_view(ptr, n):
+    import torch
+    return P.device_view(ptr, n, 1, torch.int64)   # uint64 counters, small values
+
+
+@pytest.mark.parametrize("ncols", [16, 1])
+def test_partition_ready_counters(ncols):
+    """Per-message completion counters: after the k-th pack each counter
+    equals k times its message size; the packed data stay exact; batches with
+    such members pack in the pull form and the tuner's trials do not count."""
+    need_gpu()
+    import torch
+    (b0, h0, l0), (b1, h1, l1), (b2, h2, l2) = small_plans()[2:5]
+    say("ready counters", ncols)
+    reqs = []
+    for b, h, lists in ((b0, h0, l0), (b1, h1, l1), (b2, h2, l2)):
+        req, x, halo = make_req(lists, h, ncols, torch.float64, 900 + b)
+        reqs.append((req, x, halo, lists))
+    ptrs = [P.hx_req_enable_ready(r[0]) for r in reqs[:2]]     # the third member keeps no counters
+    assert ptrs[0] == P.hx_req_enable_ready(reqs[0][0])      # enabling twice keeps the counters
+    counts = [np.asarray(r[3]["counts"], np.int64) for r in reqs[:2]]
+    # single request, three Start/Wait rounds
+    req, x, halo, lists = reqs[0]
+    for k in (1, 2, 3):
+        P.hx_start(req)
+        P.hx_wait(req)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(counters_view(ptrs[0], counts[0].size))[:, 0], k * counts[0])
+    send = host(P.req_arena_view(req, P.HX_ARENA_SEND, ncols, torch.float64))
+    assert bits_equal(send, OM.pack(host(x), lists["send_idx"]))
+    # batch of the three members: default schedule, then tuned
+    bt = P.hx_batch_init([r[0] for r in reqs])
+    assert P.hx_batch_get_sched(bt, 0)["push_pack"] == 2
+    P.hx_batch_start(bt)
+    P.hx_batch_wait(bt)
+    P.hx_batch_tune(bt)
+    P.hx_batch_start(bt)
+    P.hx_batch_wait(bt)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(counters_view(ptrs[0], counts[0].size))[:, 0], 5 * counts[0])
+    assert np.array_equal(host(counters_view(ptrs[1], counts[1].size))[:, 0], 2 * counts[1])
+    for req, x, halo, lists in reqs:
+        send = host(P.req_arena_view(req, P.HX_ARENA_SEND, ncols, torch.float64))
+        assert bits_equal(send, OM.pack(host(x), lists["send_idx"]))
+    bt.free()
