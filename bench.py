@@ -212,9 +212,11 @@ def setup_world(args, torch, P, name):
 def time_steps(torch, P, batch, steps, warmup, plain, phases):
     """Times `steps` steps (Start + Wait [+ backward when 3 is in phases]);
     a backward outside the step is timed afterwards for the report only."""
-    run = {0: P.hx_batch_start_plain if plain else P.hx_batch_start,
+    sp = torch.cuda.current_stream().cuda_stream   # passed explicitly: no stream lookup per call
+    fns = {0: P.hx_batch_start_plain if plain else P.hx_batch_start,
            2: P.hx_batch_wait_plain if plain else P.hx_batch_wait,
            3: P.hx_batch_backward_plain if plain else P.hx_batch_backward}
+    run = {k: (lambda b, f=f: f(b, sp)) for k, f in fns.items()}
     with_bwd = 3 in phases
     for _ in range(warmup):
         run[0](batch)

@@ -8,8 +8,12 @@
 // -- and the rows they share -- stay in one XCD's L2, and each XCD streams a
 // contiguous stretch of memory.  Rows move as 16/8/4-byte vectors with LPR
 // lanes per row; U rows per lane are loaded before any is stored, to keep
-// enough bytes in flight for HBM.  Pure data movement (plus adds in the
-// segmented sum): no matrix cores are involved.
+// enough bytes in flight for HBM.  LDS carries the rest: CSR-driven kernels
+// stage each tile's row pointers and entry indices (the push pack then runs
+// entry-parallel; the segmented sum gathers a chunk's terms entry-parallel
+// and adds them per row from LDS), and short-row gathers and sums can stage
+// a job's whole source window.  Pure data movement (plus adds in the
+// segmented sums): no matrix cores are involved.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -4,8 +4,12 @@
 //   send_all = [stage-1 send of rank 0, 1, ... | stage-2 send of rank 0, 1, ...]
 //   recv_all = [stage-1 recv of rank 0, 1, ... | stage-2 recv of rank 0, 1, ...]
 // and turns each phase into one gather over global row indices, so a phase
-// of all ranks is a single launch.  The simulated transfer of a stage is one
-// more gather, from each sender's message segment into the receiver's slots.
+// of all ranks is a single launch (one job per rank where the job's LDS
+// window is its own rank's rows or arena).  The simulated transfer of a stage
+// is one more gather, from each sender's message segment into the receiver's
+// slots.  The backward is the closed-form adjoint over halo_all rows, or, for
+// a locality plan with HX_WORLD_STAGED_BACKWARD, the forward's stages in
+// reverse (forwarder sums, then owner sums).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
