@@ -8,10 +8,12 @@ the backward of the pack (fixed-order transpose sum), each phase one
 persistent kernel replayed from a hipGraph.  The same work as one launch per
 plan per phase ("plain") is timed beside it.
 
-Other workloads (``--workload``): random_rows (2^22 x 32 random matrix,
-4096 ranks, locality-aware plan, every rank batched), grid3d (27-point 128^3,
-512 ranks), grid2d (5-point 512^2, 16 ranks), diff64 (random_rows plan, 64
-FP32 features, forward + backward).
+Other workloads (``--workload``): random_rows / random_rows_f32 (2^22 x 32
+random matrix, 4096 ranks, locality-aware plan, every rank batched, one FP64
+/ FP32 column; forward step, the staged backward reported aside), grid3d
+(27-point 128^3, 512 ranks), grid2d (5-point 512^2, 16 ranks), diff64
+(random-matrix plain plan, 64 FP32 features, forward + backward), copy (the
+1 GiB calibration copy for the PMC scale factors).
 
 Prints one JSON line (rank 0, one GPU).
 """
@@ -148,7 +150,7 @@ def setup_world(args, torch, P, name):
     import numpy as np
     from workloads import equal_row_starts, grid2d_5pt, grid3d_27pt, random_rows, uniform_pm1, uniform_pm1_f32
     t0 = time.time()
-    if name in ("random_rows", "diff64"):
+    if name in ("random_rows", "random_rows_f32", "diff64"):
         rp, cols = random_rows()
         rs, ppn = equal_row_starts(1 << 22, 4096), 128
     elif name == "grid3d":
@@ -172,6 +174,9 @@ def setup_world(args, torch, P, name):
     if name == "diff64":
         C, dt = 64, torch.float32
         x = torch.from_numpy(uniform_pm1_f32(7337, n * C).reshape(n, C)).cuda()
+    elif name == "random_rows_f32":
+        C, dt = 1, torch.float32
+        x = torch.from_numpy(uniform_pm1_f32(7337, n).reshape(n, 1)).cuda()
     else:
         C, dt = 1, torch.float64
         x = torch.from_numpy(uniform_pm1(7337, n).reshape(n, 1)).cuda()
@@ -195,6 +200,8 @@ def setup_world(args, torch, P, name):
         P.hx_batch_tune(batch)
     cfg = {"workload": {"random_rows": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality "
                                        "2-step, all ranks batched, 1 x FP64",
+                        "random_rows_f32": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality "
+                                           "2-step, all ranks batched, 1 x FP32",
                         "grid3d": "27-point 128^3, 512 ranks, 64/node, locality 2-step, all ranks, 1 x FP64",
                         "grid2d": "5-point 512^2, 16 ranks, 4/node, locality 2-step, all ranks, 1 x FP64",
                         "diff64": "random 2^22 x 32, 4096 ranks, plain plan, 64 x FP32 features, forward "
@@ -204,7 +211,7 @@ def setup_world(args, torch, P, name):
     # forward (pack / redistribution / unpack) workloads, backward reported aside
     phases = (0, 1, 2, 3) if name == "diff64" else (0, 1, 2)
     cfg["step"] = "pack + redistribution + unpack" + (" + backward" if 3 in phases else "")
-    return dict(batch=batch, members=None, host=[], dtype="f64" if C == 1 else "f32", cfg=cfg,
+    return dict(batch=batch, members=None, host=[], dtype="f64" if dt == torch.float64 else "f32", cfg=cfg,
                 phases=phases, keep=(plan, x, halo, g_halo, g_x))
 
 
@@ -311,7 +318,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched256",
-                    choices=["batched256", "random_rows", "grid3d", "grid2d", "diff64", "copy"])
+                    choices=["batched256", "random_rows", "random_rows_f32", "grid3d", "grid2d", "diff64", "copy"])
     ap.add_argument("--plans", type=int, default=256)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
