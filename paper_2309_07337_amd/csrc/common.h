@@ -122,7 +122,7 @@ Sched default_sched(int kind, int row_bytes);
 // of consecutive rows into kSegValueBytes of LDS before adding them.
 constexpr int kStageRows = 512;
 constexpr int kStageEntries = 2048;
-constexpr int kSegValueBytes = 32768;
+constexpr int kSegValueBytes = 65536;
 // Largest source window a gather stages in LDS (larger ones read global
 // memory): two such workgroups fit in the 160 KiB of a gfx950 CU.
 constexpr int kWinBytes = 80 << 10;
