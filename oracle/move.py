@@ -60,7 +60,9 @@ def forward_all(plans: list, x_global: np.ndarray, row_starts) -> dict:
     """
     R = len(plans)
     rs = np.asarray(row_starts, np.int64)
-    send1 = [pack(x_global[rs[p]:rs[p + 1]], plans[p]["s1_idx"]) for p in range(R)]
+    # pack indices are rows from the rank's first row, or from its node's
+    # first row for the 3-step plan (``pack_base``)
+    send1 = [pack(x_global[int(plans[p].get("pack_base", rs[p])):], plans[p]["s1_idx"]) for p in range(R)]
     recv1 = transfer(send1, [(p["s1_procs"], p["s1_counts"], p["s1_displs"]) for p in plans],
                      [(p["r1_procs"], p["r1_counts"], p["r1_displs"]) for p in plans])
     send2 = [gather_rows(recv1[p], plans[p]["s2_src"]) for p in range(R)]
@@ -182,10 +184,13 @@ def staged_adjoint_reference(plans: list, g_halos: list, row_starts) -> dict:
         g_recv1.append(segmented_sum_fixed_order(vals, np.asarray(ptr, np.int64), np.asarray(order, np.int64)))
     g_send1 = reverse_transfer(g_recv1, [(p["s1_procs"], p["s1_counts"], p["s1_displs"]) for p in plans],
                                [(p["r1_procs"], p["r1_counts"], p["r1_displs"]) for p in plans])
-    gx = []
-    for r in range(R):
-        n_r = int(rs[r + 1] - rs[r])
-        ptr, perm = transpose_csr(plans[r]["s1_idx"], n_r)
-        gx.append(pack_transpose(g_send1[r], ptr, perm) if n_r else np.zeros((0,) + tail, dt))
-    g_x = np.concatenate(gx, axis=0) if R else np.zeros((0,) + tail, dt)
+    # owner sums over every rank's stage-1 send slots, keyed by global row,
+    # ascending (rank, slot): per rank the pack transpose when only the owner
+    # packs its rows (plain, 2-step), the node's senders in rank order (3-step)
+    n = int(rs[-1]) if R else 0
+    keys = [int(plans[r].get("pack_base", rs[r])) + np.asarray(plans[r]["s1_idx"], np.int64) for r in range(R)]
+    keys = np.concatenate(keys) if R else np.zeros(0, np.int64)
+    vals = np.concatenate(g_send1, axis=0) if R else np.zeros((0,) + tail, dt)
+    ptr, perm = transpose_csr(keys, n)
+    g_x = pack_transpose(vals, ptr, perm)
     return dict(g_x=g_x, g_recv2=g_recv2, g_send2=g_send2, g_recv1=g_recv1, g_send1=g_send1)

@@ -283,11 +283,154 @@ class Decomposition:
                     unpack_src=unpack.astype(I32),
                     bt_ptr=bt_ptr, bt_perm=bt_perm)
 
+    # --- locality-aware 3-step variant (Sec. 2.2, aggregation; reading R16) -
+    def node_start(self, n: int) -> int:
+        return int(self.row_starts[n * self.ppn])
+
+    def node_rows(self, n: int) -> int:
+        return int(self.row_starts[n * self.ppn + self.cnt(n)]) - self.node_start(n)
+
+    def aggregator(self, n: int, m: int) -> int:
+        """Rank of node n that sends node n's data for node m (reading R16)."""
+        return n * self.ppn + (m % self.cnt(n))
+
+    def receiver(self, n: int, m: int) -> int:
+        """Rank of node m that receives node n's data (reading R16)."""
+        return m * self.ppn + (n % self.cnt(m))
+
+    def node_seg(self, s: int, n: int) -> np.ndarray:
+        """N_s restricted to the columns owned by node n (ascending)."""
+        h = self.halos[s]
+        lo, hi = np.searchsorted(h, [self.node_start(n), self.node_start(n) + self.node_rows(n)])
+        return h[lo:hi]
+
+    def node_dedup(self, n: int, m: int) -> np.ndarray:
+        """D(n -> m): distinct columns of node n needed by any rank of node m."""
+        parts = [self.node_seg(s, n) for s in self.node_ranks(m)]
+        parts = [p for p in parts if p.size]
+        if not parts:
+            return np.zeros(0, np.int64)
+        return np.unique(np.concatenate(parts))
+
+    def received_nodes(self, t: int) -> list:
+        """Remote nodes whose node-pair message to node(t) lands on t, ascending."""
+        n = self.node(t)
+        return [m for m in range(self.nnodes()) if m != n and self.receiver(m, n) == t]
+
+    def locality3_plan(self, r: int) -> dict:
+        """Plan of rank r for the 3-step locality-aware variant (reading R16).
+
+        Stage 1 carries the direct on-node messages and, from each node
+        pair's aggregator, one message with the node's deduplicated data for
+        the other node (the aggregator packs its node-mates' rows directly,
+        so the on-node gather is part of its pack); stage 2 is the
+        receiver's redistribution.  Pack indices are rows of the node
+        (``pack_base`` = the node's first row).
+        """
+        n = self.node(r)
+        base = self.node_start(n)
+        msgs = []
+        for s in self.node_ranks(n):
+            if s != r:
+                g = self.seg(s, r)
+                if g.size:
+                    msgs.append((s, g - base))
+        for m in range(self.nnodes()):
+            if m != n and self.aggregator(n, m) == r:
+                d = self.node_dedup(n, m)
+                if d.size:
+                    msgs.append((self.receiver(n, m), d - base))
+        msgs.sort(key=lambda t: t[0])
+        s1p, s1c, s1d = _lists([t for t, _ in msgs], [len(v) for _, v in msgs])
+        s1_idx = np.concatenate([v for _, v in msgs]).astype(I32) if msgs else np.zeros(0, I32)
+
+        # stage 1, receive side: direct messages and node-pair messages (by sender)
+        rmsgs = []
+        for q in self.node_ranks(n):
+            if q != r:
+                g = self.seg(r, q)
+                if g.size:
+                    rmsgs.append((q, g))
+        fwd = self.received_nodes(r)
+        for m in fwd:
+            d = self.node_dedup(m, n)
+            if d.size:
+                rmsgs.append((self.aggregator(m, n), d))
+        rmsgs.sort(key=lambda t: t[0])
+        r1p, r1c, r1d = _lists([q for q, _ in rmsgs], [len(v) for _, v in rmsgs])
+        r1_slot = {int(q): int(d) for q, d in zip(r1p, r1d)}
+        r1_ids = {int(q): v for q, v in rmsgs}
+        R1 = int(r1c.sum()) if r1c.size else 0
+
+        # stage 2, send side: r forwards to each other rank s of its node the
+        # entries of N_s owned by the nodes whose message landed on r
+        s2 = []
+        for s in self.node_ranks(n):
+            if s == r:
+                continue
+            src = []
+            for m in fwd:
+                g = self.node_seg(s, m)
+                if g.size:
+                    a = self.aggregator(m, n)
+                    src.append(r1_slot[a] + np.searchsorted(r1_ids[a], g))
+            if src:
+                s2.append((s, np.concatenate(src)))
+        s2p, s2c, s2d = _lists([s for s, _ in s2], [len(v) for _, v in s2])
+        s2_src = np.concatenate([v for _, v in s2]).astype(I32) if s2 else np.zeros(0, I32)
+
+        # stage 2, receive side: node by node (ascending) within each forwarder
+        r2 = []
+        run_start = {}
+        for t in self.node_ranks(n):
+            if t == r:
+                continue
+            c = 0
+            for m in self.received_nodes(t):
+                run_start[m] = (t, c)
+                c += self.node_seg(r, m).size
+            if c:
+                r2.append((t, c))
+        r2p, r2c, r2d = _lists([t for t, _ in r2], [c for _, c in r2])
+        r2_slot = {int(t): int(d) for t, d in zip(r2p, r2d)}
+
+        # unpack
+        h = self.halos[r]
+        unpack = np.empty(h.size, np.int64)
+        own = owner(h, self.row_starts)
+        onode = own // self.ppn
+        for m in np.unique(onode):
+            m = int(m)
+            sel = np.nonzero(onode == m)[0]
+            cols_m = h[sel]
+            if m == n:
+                for q in np.unique(own[sel]):
+                    q = int(q)
+                    sq = sel[own[sel] == q]
+                    unpack[sq] = r1_slot[q] + np.searchsorted(r1_ids[q], h[sq])
+            elif self.receiver(m, n) == r:
+                a = self.aggregator(m, n)
+                unpack[sel] = r1_slot[a] + np.searchsorted(r1_ids[a], cols_m)
+            else:
+                t, c0 = run_start[m]
+                unpack[sel] = R1 + r2_slot[t] + c0 + np.arange(sel.size)
+
+        bt_ptr, bt_perm = transpose_csr(s1_idx, self.node_rows(n))
+        return dict(halo=h.copy(),
+                    s1_procs=s1p, s1_counts=s1c, s1_displs=s1d, s1_idx=s1_idx,
+                    r1_procs=r1p, r1_counts=r1c, r1_displs=r1d,
+                    s2_procs=s2p, s2_counts=s2c, s2_displs=s2d, s2_src=s2_src,
+                    r2_procs=r2p, r2_counts=r2c, r2_displs=r2d,
+                    unpack_src=unpack.astype(I32),
+                    bt_ptr=bt_ptr, bt_perm=bt_perm, pack_base=base)
+
     def plan(self, r: int, variant: str) -> dict:
         if variant == "plain":
             return self.plain_plan(r)
         if variant == "locality":
             return self.locality_plan(r)
+        if variant == "locality3":
+            return self.locality3_plan(r)
         raise ValueError(variant)
 
 

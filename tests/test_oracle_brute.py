@@ -351,3 +351,121 @@ def test_staged_adjoint_locality_exact_values(case):
     x = (np.arange(n * 2) % 9 - 4).astype(np.float64).reshape(n, 2)
     fw = M.forward_all(plans, x, rs)["halo"]
     assert sum(float(np.sum(a * b)) for a, b in zip(fw, gy)) == float(np.sum(x * got))
+
+
+# --- the 3-step variant (reading R16) ----------------------------------------
+def _node_of(row_starts, c, ppn):
+    return int(np.searchsorted(row_starts, c, side="right") - 1) // ppn
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_locality3_exchange_and_node_pairs(case):
+    """3-step plan: the exchange equals the direct gather x[N_r]; exactly one
+    inter-node message per node pair that needs one, from the pair's
+    aggregator to its receiver, carrying the node's distinct columns the
+    other node needs (Python sets, written from the definitions)."""
+    rs, rp, cols, halos, D = build(case)
+    n, R, ppn = int(rs[-1]), len(rs) - 1, case[-1]
+    NN = (R + ppn - 1) // ppn
+    cnt = [min(ppn, R - m * ppn) for m in range(NN)]
+    plans = [D.plan(r, "locality3") for r in range(R)]
+    x = (np.arange(n * 2) + 1).astype(np.float64).reshape(n, 2)
+    out = M.forward_all(plans, x, rs)
+    for r in range(R):
+        assert np.array_equal(out["halo"][r], x[halos[r]])
+    need = {}   # (source node, destination node) -> set of columns
+    for s in range(R):
+        for c in np.asarray(halos[s]).tolist():
+            a, b = _node_of(rs, c, ppn), s // ppn
+            if a != b:
+                need.setdefault((a, b), set()).add(c)
+    seen = {}
+    for r in range(R):
+        p = plans[r]
+        base = p["pack_base"]
+        for q, cnt_, d in zip(p["s1_procs"], p["s1_counts"], p["s1_displs"]):
+            if int(q) // ppn == r // ppn:
+                continue
+            key = (r // ppn, int(q) // ppn)
+            assert key not in seen, "two messages for one node pair"
+            seen[key] = (r, int(q), set((base + p["s1_idx"][int(d):int(d) + int(cnt_)]).tolist()))
+    assert set(seen) == set(need)
+    for (a, b), (snd, rcv, colset) in seen.items():
+        assert snd == a * ppn + b % cnt[a] and rcv == b * ppn + a % cnt[b]
+        assert colset == need[(a, b)]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_locality3_special_cases(case):
+    """One rank per node: the 3-step plan is the plain plan (each node pair is
+    a rank pair).  One node: no inter-node traffic, so it is the 2-step plan
+    (same messages, pack indices from the node's first row)."""
+    rs, rp, cols, halos, _ = build(case)
+    R = len(rs) - 1
+    D1 = P.Decomposition(halos, rs, 1)
+    for r in range(R):
+        a, b = D1.plan(r, "locality3"), D1.plan(r, "plain")
+        for k in ("s1_procs", "s1_counts", "r1_procs", "r1_counts", "s2_counts", "r2_counts"):
+            assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a["s1_idx"].astype(np.int64) + a["pack_base"] - rs[r], b["s1_idx"])
+        assert np.array_equal(a["unpack_src"], b["unpack_src"])
+    DA = P.Decomposition(halos, rs, R)
+    for r in range(R):
+        a, b = DA.plan(r, "locality3"), DA.plan(r, "locality")
+        for k in ("s1_procs", "s1_counts", "r1_procs", "r1_counts", "s2_counts", "r2_counts", "unpack_src"):
+            assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a["s1_idx"].astype(np.int64) + a["pack_base"], b["s1_idx"] + rs[r])
+
+
+def brute_staged_expression3(halos, row_starts, ppn):
+    """Expected gradient expression of every row under R15 on the 3-step plan
+    (R16): the slots of row c are the owner's direct on-node slots and one
+    node-pair slot per remote node needing c, held by that pair's
+    aggregator; the receiver sums its own need first, then its node's other
+    needers ascending; slots add in ascending (sender rank, destination)."""
+    R = len(row_starts) - 1
+    NN = (R + ppn - 1) // ppn
+    cnt = [min(ppn, R - m * ppn) for m in range(NN)]
+    needers = {}
+    for s, h in enumerate(halos):
+        for c in np.asarray(h).tolist():
+            needers.setdefault(c, []).append(s)
+    out = {}
+    for c, ss in needers.items():
+        p = int(np.searchsorted(row_starts, c, side="right") - 1)
+        n = p // ppn
+        slots = {}   # (sender, destination) -> needers served
+        for s in ss:
+            m = s // ppn
+            if m == n:
+                slots[(p, s)] = [s]
+            else:
+                a, b = n * ppn + m % cnt[n], m * ppn + n % cnt[m]
+                slots.setdefault((a, b), []).append(s)
+        terms = []
+        for key in sorted(slots):
+            grp = sorted(slots[key])
+            dest = key[1]
+            grp = ([dest] if dest in grp else []) + [s for s in grp if s != dest]
+            terms.append(_fold([Sym(f"g{s}_{c}") for s in grp]))
+        out[c] = _fold(terms)
+    return out
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_locality3_staged_adjoint(case):
+    """Staged backward on the 3-step plan: the order the reading prescribes
+    (symbolic brute force), and the closed form in exact arithmetic."""
+    rs, rp, cols, halos, D = build(case)
+    n, R, ppn = int(rs[-1]), len(rs) - 1, case[-1]
+    plans = [D.plan(r, "locality3") for r in range(R)]
+    gy = [np.array([Sym(f"g{r}_{c}") for c in np.asarray(h).tolist()], dtype=object) for r, h in enumerate(halos)]
+    got = M.staged_adjoint_reference(plans, gy, rs)["g_x"]
+    want = brute_staged_expression3(halos, rs, ppn)
+    for c in range(n):
+        if c in want:
+            assert got[c] == want[c], (c, got[c], want[c])
+        else:
+            assert not isinstance(got[c], Sym) and got[c] == 0
+    gi = [((np.arange(h.size) * 5 + r) % 9 - 4).astype(np.float64) for r, h in enumerate(halos)]
+    assert np.array_equal(M.staged_adjoint_reference(plans, gi, rs)["g_x"], M.exchange_adjoint_reference(halos, gi, n))
