@@ -61,7 +61,15 @@ enum {
 };
 
 typedef enum { HX_F32 = 0, HX_F64 = 1 } hx_dtype;
-typedef enum { HX_PLAIN = 0, HX_LOCALITY_2STEP = 1 } hx_variant;
+/* Plan variants.  HX_PLAIN: one message per rank pair.  HX_LOCALITY_2STEP:
+ * each rank sends its node-deduplicated data to one partner per remote node,
+ * which redistributes it on its node.  HX_LOCALITY_3STEP: one message per
+ * node pair, sent by the pair's aggregator A(n,m) = n*ppn + (m mod cnt(n))
+ * to its receiver B(n,m) = m*ppn + (n mod cnt(m)); the aggregator packs its
+ * node-mates' rows directly (node-shared memory), so its pack indices are
+ * rows counted from the node's first row and such plans drive whole-
+ * decomposition batches only (hx_req_from_plan returns HX_ERR_UNSUPPORTED). */
+typedef enum { HX_PLAIN = 0, HX_LOCALITY_2STEP = 1, HX_LOCALITY_3STEP = 2 } hx_variant;
 
 typedef struct hx_topo hx_topo;
 typedef struct hx_plan hx_plan;

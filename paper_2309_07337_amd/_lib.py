@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libhx.so")
 HX_SUCCESS = 0
 HX_ERR_ARG, HX_ERR_RANGE, HX_ERR_STATE, HX_ERR_NOMEM, HX_ERR_UNSUPPORTED, HX_ERR_HIP = -1, -2, -3, -4, -5, -6
 HX_F32, HX_F64 = 0, 1
-HX_PLAIN, HX_LOCALITY_2STEP = 0, 1
+HX_PLAIN, HX_LOCALITY_2STEP, HX_LOCALITY_3STEP = 0, 1, 2
 HX_ARENA_SEND, HX_ARENA_RECV, HX_ARENA_GRAD_SEND = 0, 1, 4
 HX_WORLD_SIM_TRANSFER, HX_WORLD_STAGED_BACKWARD = 1, 2
 HX_PLAN_MAX_RANKS = 16384

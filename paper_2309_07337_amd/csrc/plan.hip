@@ -53,6 +53,22 @@ __device__ __forceinline__ int node_cnt(int m, int ppn, int R) { return min(ppn,
 __device__ __forceinline__ int partner_of(int q, int m, int ppn, int R) {
   return m * ppn + (q % ppn) % node_cnt(m, ppn, R);
 }
+// 3-step (one message per node pair): the rank of node n that sends node n's
+// data for node m, and the rank of node m that receives it.
+__device__ __forceinline__ int aggr_of(int n, int m, int ppn, int R) { return n * ppn + m % node_cnt(n, ppn, R); }
+__device__ __forceinline__ int recv_of(int n, int m, int ppn, int R) { return m * ppn + n % node_cnt(m, ppn, R); }
+// The forwarder on node m of the entries owned by rank q (the rank their
+// aggregated stage-1 message lands on), the sender of that message, and the
+// first row of the column range the message deduplicates over.
+__device__ __forceinline__ int fwd_of(int q, int m, int ppn, int R, int v3) {
+  return v3 ? recv_of(q / ppn, m, ppn, R) : partner_of(q, m, ppn, R);
+}
+__device__ __forceinline__ int agg_sender(int q, int m, int ppn, int R, int v3) {
+  return v3 ? aggr_of(q / ppn, m, ppn, R) : q;
+}
+__device__ __forceinline__ int64_t agg_base(int q, const int64_t* __restrict__ rs, int ppn, int v3) {
+  return v3 ? rs[(q / ppn) * ppn] : rs[q];
+}
 
 template <class T>
 __device__ T wave_sum(T v) {
@@ -389,16 +405,23 @@ __global__ void k_word_exscan(const uint32_t* __restrict__ NB, int64_t W1, int32
   }
 }
 
-// MD[m][q] = |D(q -> m)| for q off node m (else 0).
+// MD[m][q] = |D(q -> m)| for q off node m (else 0).  3-step: |D(n -> m)| of
+// q's node n at q = the pair's aggregator (else 0).
 __global__ void k_dedup_counts(const uint32_t* __restrict__ NB, const int32_t* __restrict__ NBP, int64_t W1,
-                               const int64_t* __restrict__ rs, int R, int NN, int ppn, int32_t* MD) {
+                               const int64_t* __restrict__ rs, int R, int NN, int ppn, int v3, int32_t* MD) {
   GRID_STRIDE(i, (int64_t)NN * R) {
     const int m = (int)(i / R), q = (int)(i % R);
     int32_t v = 0;
     if (q / ppn != m) {
       const uint32_t* nb = NB + (size_t)m * W1;
       const int32_t* np = NBP + (size_t)m * W1;
-      v = bit_rank(nb, np, rs[q + 1]) - bit_rank(nb, np, rs[q]);
+      if (!v3) {
+        v = bit_rank(nb, np, rs[q + 1]) - bit_rank(nb, np, rs[q]);
+      } else {
+        const int n = q / ppn;
+        if (q == aggr_of(n, m, ppn, R))
+          v = bit_rank(nb, np, rs[min(R, (n + 1) * ppn)]) - bit_rank(nb, np, rs[n * ppn]);
+      }
     }
     MD[i] = v;
   }
@@ -406,14 +429,15 @@ __global__ void k_dedup_counts(const uint32_t* __restrict__ NB, const int32_t* _
 
 // Stage-1 message sizes S1[q][d]: direct to on-node d, deduplicated to partners.
 __global__ void k_stage1_sizes(const int32_t* __restrict__ MT, const int32_t* __restrict__ MD, int R, int ppn,
-                               int32_t* S1) {
+                               int v3, int32_t* S1) {
   GRID_STRIDE(i, (int64_t)R * R) {
     const int q = (int)(i / R), d = (int)(i % R);
     int32_t v = 0;
     if (d != q) {
       const int nq = q / ppn, nd = d / ppn;
       if (nq == nd) v = MT[i];
-      else if (d == partner_of(q, nd, ppn, R)) v = MD[(size_t)nd * R + q];
+      else if (v3 ? (q == aggr_of(nq, nd, ppn, R) && d == recv_of(nq, nd, ppn, R)) : d == partner_of(q, nd, ppn, R))
+        v = MD[(size_t)nd * R + q];
     }
     S1[i] = v;
   }
@@ -421,7 +445,7 @@ __global__ void k_stage1_sizes(const int32_t* __restrict__ MT, const int32_t* __
 
 // Stage-2 message sizes S2[t][s] (t forwards to s on its node): the entries of
 // N_s owned by remote ranks whose aggregated message lands on t.
-__global__ void k_stage2_sizes(const int32_t* __restrict__ M, int R, int ppn, int NN, int32_t* S2) {
+__global__ void k_stage2_sizes(const int32_t* __restrict__ M, int R, int ppn, int NN, int v3, int32_t* S2) {
   GRID_STRIDE(i, (int64_t)R * R) {
     const int t = (int)(i / R), s = (int)(i % R);
     int64_t v = 0;
@@ -433,7 +457,12 @@ __global__ void k_stage2_sizes(const int32_t* __restrict__ M, int R, int ppn, in
       for (int m = 0; m < NN; ++m) {
         if (m == n) continue;
         const int cm = node_cnt(m, ppn, R);
-        for (int l = lt; l < cm; l += cn) v += Ms[m * ppn + l];
+        if (v3) {  // every rank of the nodes whose pair message lands on t
+          if (m % cn == lt)
+            for (int l = 0; l < cm; ++l) v += Ms[m * ppn + l];
+        } else {
+          for (int l = lt; l < cm; l += cn) v += Ms[m * ppn + l];
+        }
       }
     }
     S2[i] = (int32_t)v;
@@ -442,7 +471,7 @@ __global__ void k_stage2_sizes(const int32_t* __restrict__ M, int R, int ppn, in
 
 // QP[s][q]: for q off s's node, the number of entries of N_s owned by the
 // ranks before q (ascending) that share q's partner on s's node.
-__global__ void k_class_prefix(const int32_t* __restrict__ M, int R, int ppn, int NN, int32_t* QP) {
+__global__ void k_class_prefix(const int32_t* __restrict__ M, int R, int ppn, int NN, int v3, int32_t* QP) {
   GRID_STRIDE(i, (int64_t)R * ppn) {
     const int s = (int)(i / ppn), l0 = (int)(i % ppn);
     const int n = s / ppn;
@@ -454,10 +483,19 @@ __global__ void k_class_prefix(const int32_t* __restrict__ M, int R, int ppn, in
     for (int m = 0; m < NN; ++m) {
       if (m == n) continue;
       const int cm = node_cnt(m, ppn, R);
-      for (int l = l0; l < cm; l += cn) {
-        const int q = m * ppn + l;
-        Qs[q] = run;
-        run += Ms[q];
+      if (v3) {  // class l0: the nodes m with m mod cn == l0, every rank of each
+        if (m % cn != l0) continue;
+        for (int l = 0; l < cm; ++l) {
+          const int q = m * ppn + l;
+          Qs[q] = run;
+          run += Ms[q];
+        }
+      } else {
+        for (int l = l0; l < cm; l += cn) {
+          const int q = m * ppn + l;
+          Qs[q] = run;
+          run += Ms[q];
+        }
       }
     }
   }
@@ -470,7 +508,7 @@ __global__ void k_class_prefix(const int32_t* __restrict__ M, int R, int ppn, in
 // the on-node ones (locality).
 __global__ void k_s1_direct(const int32_t* __restrict__ hcol, const int32_t* __restrict__ hrank,
                             const int32_t* __restrict__ own, int64_t nH, const int64_t* __restrict__ hoff,
-                            const int64_t* __restrict__ rs, int R, int ppn, int onnode_only,
+                            const int64_t* __restrict__ rs, int R, int ppn, int onnode_only, int v3,
                             const int32_t* __restrict__ PS1, const int32_t* __restrict__ PM,
                             const int64_t* __restrict__ s1_off, int32_t* s1_idx, int* err) {
   GRID_STRIDE(e, nH) {
@@ -482,13 +520,13 @@ __global__ void k_s1_direct(const int32_t* __restrict__ hcol, const int32_t* __r
       atomicOr(err, 32);
       continue;
     }
-    s1_idx[pos] = (int32_t)(hcol[e] - rs[q]);
+    s1_idx[pos] = (int32_t)(hcol[e] - agg_base(q, rs, ppn, v3));  // 3-step: rows of the node
   }
 }
 
 // Stage-1 aggregated entries: one per set bit of a node bitmap owned off-node.
 __global__ void k_s1_agg(const uint32_t* __restrict__ NB, const int32_t* __restrict__ NBP, int64_t W1,
-                         int64_t W, int NN, const int64_t* __restrict__ rs, int R, int ppn,
+                         int64_t W, int NN, const int64_t* __restrict__ rs, int R, int ppn, int v3,
                          const int32_t* __restrict__ PS1, const int64_t* __restrict__ s1_off, int32_t* s1_idx,
                          int* err) {
   GRID_STRIDE(i, (int64_t)NN * W) {
@@ -503,13 +541,15 @@ __global__ void k_s1_agg(const uint32_t* __restrict__ NB, const int32_t* __restr
       const int64_t c = w * 32 + b;
       const int q = upper_rank(rs, R, c);
       if (q / ppn == m) continue;
-      const int t = partner_of(q, m, ppn, R);
-      const int64_t pos = s1_off[q] + PS1[(size_t)q * R + t] + (bit_rank(nb, np, c) - bit_rank(nb, np, rs[q]));
-      if (pos < s1_off[q] || pos >= s1_off[q + 1]) {
+      const int t = fwd_of(q, m, ppn, R, v3);
+      const int a = agg_sender(q, m, ppn, R, v3);
+      const int64_t base = agg_base(q, rs, ppn, v3);
+      const int64_t pos = s1_off[a] + PS1[(size_t)a * R + t] + (bit_rank(nb, np, c) - bit_rank(nb, np, base));
+      if (pos < s1_off[a] || pos >= s1_off[a + 1]) {
         atomicOr(err, 32);
         continue;
       }
-      s1_idx[pos] = (int32_t)(c - rs[q]);
+      s1_idx[pos] = (int32_t)(c - base);
     }
   }
 }
@@ -522,12 +562,12 @@ __global__ void k_s2_src(const int32_t* __restrict__ hcol, const int32_t* __rest
                          const int32_t* __restrict__ QP, const int32_t* __restrict__ PM,
                          const int32_t* __restrict__ PR1, const uint32_t* __restrict__ NB,
                          const int32_t* __restrict__ NBP, int64_t W1, const int64_t* __restrict__ s2_off,
-                         int32_t* s2_src, int* err) {
+                         int v3, int32_t* s2_src, int* err) {
   GRID_STRIDE(e, nH) {
     const int s = hrank[e], q = own[e];
     const int n = s / ppn;
     if (q / ppn == n) continue;
-    const int t = partner_of(q, n, ppn, R);
+    const int t = fwd_of(q, n, ppn, R, v3);
     if (t == s) continue;
     const int64_t j = e - hoff[s];
     const int64_t c = hcol[e];
@@ -538,14 +578,15 @@ __global__ void k_s2_src(const int32_t* __restrict__ hcol, const int32_t* __rest
       atomicOr(err, 32);
       continue;
     }
-    s2_src[pos] = PR1[(size_t)t * R + q] + (bit_rank(nb, np, c) - bit_rank(nb, np, rs[q]));
+    s2_src[pos] = PR1[(size_t)t * R + agg_sender(q, n, ppn, R, v3)] +
+                  (bit_rank(nb, np, c) - bit_rank(nb, np, agg_base(q, rs, ppn, v3)));
   }
 }
 
 // Unpack map: slot of each halo entry in [stage-1 recv | stage-2 recv].
 __global__ void k_unpack_map(const int32_t* __restrict__ hcol, const int32_t* __restrict__ hrank,
                              const int32_t* __restrict__ own, int64_t nH, const int64_t* __restrict__ hoff,
-                             const int64_t* __restrict__ rs, int R, int ppn, int locality,
+                             const int64_t* __restrict__ rs, int R, int ppn, int locality, int v3,
                              const int32_t* __restrict__ PM, const int32_t* __restrict__ PR1,
                              const int32_t* __restrict__ PR2, const int32_t* __restrict__ QP,
                              const uint32_t* __restrict__ NB, const int32_t* __restrict__ NBP, int64_t W1,
@@ -564,11 +605,12 @@ __global__ void k_unpack_map(const int32_t* __restrict__ hcol, const int32_t* __
     if (q / ppn == n) {
       v = PR1[(size_t)r * R + q] + (j - PM[(size_t)r * R + q]);
     } else {
-      const int t = partner_of(q, n, ppn, R);
+      const int t = fwd_of(q, n, ppn, R, v3);
       const uint32_t* nb = NB + (size_t)n * W1;
       const int32_t* np = NBP + (size_t)n * W1;
       if (t == r)
-        v = PR1[(size_t)r * R + q] + (bit_rank(nb, np, c) - bit_rank(nb, np, rs[q]));
+        v = PR1[(size_t)r * R + agg_sender(q, n, ppn, R, v3)] +
+            (bit_rank(nb, np, c) - bit_rank(nb, np, agg_base(q, rs, ppn, v3)));
       else
         v = r1_tot[r] + PR2[(size_t)r * R + t] + QP[(size_t)r * R + q] + (j - PM[(size_t)r * R + q]);
     }
@@ -579,23 +621,26 @@ __global__ void k_unpack_map(const int32_t* __restrict__ hcol, const int32_t* __
 // ---------------------------------------------------------------------------
 // Transpose of the pack map
 // ---------------------------------------------------------------------------
+// Keys of the per-rank pack transposes: rank q's pack rows occupy
+// [koff[q], koff[q+1]) of one key space (its own rows; its node's rows for
+// the 3-step plan), so one stable grouping yields every rank's transpose.
 __global__ void k_pack_keys(const int32_t* __restrict__ s1_idx, int64_t E, const int64_t* __restrict__ s1_off,
-                            const int64_t* __restrict__ rs, int R, int32_t* keys) {
+                            const int64_t* __restrict__ koff, int R, int32_t* keys) {
   GRID_STRIDE(k, E) {
     const int q = upper_rank(s1_off, R, k);
-    keys[k] = (int32_t)(rs[q] + s1_idx[k]);
+    keys[k] = (int32_t)(koff[q] + s1_idx[k]);
   }
 }
 
-// Per-rank transpose arrays from the global grouping (rows of rank q occupy
-// [rs[q], rs[q+1]) and its slots [s1_off[q], s1_off[q+1])).
+// Per-rank transpose arrays from that grouping (pack rows of rank q occupy
+// [koff[q], koff[q+1]) and its slots [s1_off[q], s1_off[q+1])).
 __global__ void k_local_bt_ptr(const int32_t* __restrict__ gptr, const int64_t* __restrict__ bt_off,
-                               const int64_t* __restrict__ rs, const int64_t* __restrict__ s1_off, int R,
+                               const int64_t* __restrict__ koff, const int64_t* __restrict__ s1_off, int R,
                                int64_t total, int32_t* bt_ptr) {
   GRID_STRIDE(i, total) {
     const int q = upper_rank(bt_off, R, i);
     const int64_t li = i - bt_off[q];
-    bt_ptr[i] = (int32_t)(gptr[rs[q] + li] - s1_off[q]);
+    bt_ptr[i] = (int32_t)(gptr[koff[q] + li] - s1_off[q]);
   }
 }
 
@@ -696,7 +741,8 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
   const int ppn = p->ppn;
   const int64_t n = p->n;
   const int64_t nH = hoff.back();
-  const bool loc = p->variant == HX_LOCALITY_2STEP;
+  const bool loc = p->variant != HX_PLAIN;
+  const int v3 = p->variant == HX_LOCALITY_3STEP ? 1 : 0;
   const int NN = (R + ppn - 1) / ppn;
   const int64_t W = (n + 31) / 32;
   const int64_t W1 = W + 1;
@@ -741,19 +787,19 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
     HX_HIP(hipGetLastError());
     HX_TRY(MD.alloc((size_t)NN * R * 4));
     hipLaunchKernelGGL(k_dedup_counts, dim3(blocks_for((int64_t)NN * R)), dim3(TB), 0, s, NB.as<uint32_t>(),
-                       NBP.as<int32_t>(), W1, p->row_starts_d.as<int64_t>(), R, NN, ppn, MD.as<int32_t>());
+                       NBP.as<int32_t>(), W1, p->row_starts_d.as<int64_t>(), R, NN, ppn, v3, MD.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(S1.A.alloc((size_t)R * R * 4));
     hipLaunchKernelGGL(k_stage1_sizes, dim3(blocks_for((int64_t)R * R)), dim3(TB), 0, s, MT.as<int32_t>(),
-                       MD.as<int32_t>(), R, ppn, S1.A.as<int32_t>());
+                       MD.as<int32_t>(), R, ppn, v3, S1.A.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(S2.A.alloc((size_t)R * R * 4));
     hipLaunchKernelGGL(k_stage2_sizes, dim3(blocks_for((int64_t)R * R)), dim3(TB), 0, s, M.A.as<int32_t>(), R,
-                       ppn, NN, S2.A.as<int32_t>());
+                       ppn, NN, v3, S2.A.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(zeros(&QP, (size_t)R * R * 4, s));
     hipLaunchKernelGGL(k_class_prefix, dim3(blocks_for((int64_t)R * ppn)), dim3(TB), 0, s, M.A.as<int32_t>(), R,
-                       ppn, NN, QP.as<int32_t>());
+                       ppn, NN, v3, QP.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(dense_transpose(S1.A, &R1.A, R, s));
     HX_TRY(dense_transpose(S2.A, &R2.A, R, s));
@@ -806,22 +852,22 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
   if (nH > 0) {
     hipLaunchKernelGGL(k_s1_direct, dim3(blocks_for(nH)), dim3(TB), 0, s, p->d[HX_F_HALO].as<int32_t>(),
                        hrank.as<int32_t>(), own.as<int32_t>(), nH, hoff_d.as<int64_t>(),
-                       p->row_starts_d.as<int64_t>(), R, ppn, loc ? 1 : 0, S1.P.as<int32_t>(), PM,
+                       p->row_starts_d.as<int64_t>(), R, ppn, loc ? 1 : 0, v3, S1.P.as<int32_t>(), PM,
                        s1o_d.as<int64_t>(), p->d[HX_F_S1_IDX].as<int32_t>(), err.as<int>());
     HX_HIP(hipGetLastError());
   }
   if (loc) {
     if (NN * W > 0) {
       hipLaunchKernelGGL(k_s1_agg, dim3(blocks_for((int64_t)NN * W)), dim3(TB), 0, s, NB.as<uint32_t>(),
-                         NBP.as<int32_t>(), W1, W, NN, p->row_starts_d.as<int64_t>(), R, ppn, S1.P.as<int32_t>(),
-                         s1o_d.as<int64_t>(), p->d[HX_F_S1_IDX].as<int32_t>(), err.as<int>());
+                         NBP.as<int32_t>(), W1, W, NN, p->row_starts_d.as<int64_t>(), R, ppn, v3,
+                         S1.P.as<int32_t>(), s1o_d.as<int64_t>(), p->d[HX_F_S1_IDX].as<int32_t>(), err.as<int>());
       HX_HIP(hipGetLastError());
     }
     if (nH > 0) {
       hipLaunchKernelGGL(k_s2_src, dim3(blocks_for(nH)), dim3(TB), 0, s, p->d[HX_F_HALO].as<int32_t>(),
                          hrank.as<int32_t>(), own.as<int32_t>(), nH, hoff_d.as<int64_t>(),
                          p->row_starts_d.as<int64_t>(), R, ppn, S2.P.as<int32_t>(), QP.as<int32_t>(), PM,
-                         R1.P.as<int32_t>(), NB.as<uint32_t>(), NBP.as<int32_t>(), W1, s2o_d.as<int64_t>(),
+                         R1.P.as<int32_t>(), NB.as<uint32_t>(), NBP.as<int32_t>(), W1, s2o_d.as<int64_t>(), v3,
                          p->d[HX_F_S2_SRC].as<int32_t>(), err.as<int>());
       HX_HIP(hipGetLastError());
     }
@@ -829,7 +875,7 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
   if (nH > 0) {
     hipLaunchKernelGGL(k_unpack_map, dim3(blocks_for(nH)), dim3(TB), 0, s, p->d[HX_F_HALO].as<int32_t>(),
                        hrank.as<int32_t>(), own.as<int32_t>(), nH, hoff_d.as<int64_t>(),
-                       p->row_starts_d.as<int64_t>(), R, ppn, loc ? 1 : 0, PM, R1.P.as<int32_t>(),
+                       p->row_starts_d.as<int64_t>(), R, ppn, loc ? 1 : 0, v3, PM, R1.P.as<int32_t>(),
                        loc ? R2.P.as<int32_t>() : nullptr, loc ? QP.as<int32_t>() : nullptr,
                        loc ? NB.as<uint32_t>() : nullptr, loc ? NBP.as<int32_t>() : nullptr, W1,
                        r1t_d.as<int64_t>(), p->d[HX_F_UNPACK_SRC].as<int32_t>());
@@ -839,26 +885,37 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
   HX_HIP(hipStreamSynchronize(s));
   HX_TRY(check_err(err, "plan lists"));
 
-  // transpose of the pack map
+  // transpose of the pack map, per rank over its pack rows (its own rows;
+  // its node's rows for the 3-step plan)
+  std::vector<int64_t> pack_rows((size_t)R);
+  for (int q = 0; q < R; ++q) {
+    const int nq = q / ppn;
+    pack_rows[q] = v3 ? p->row_starts[std::min(R, (nq + 1) * ppn)] - p->row_starts[nq * ppn]
+                      : p->row_starts[q + 1] - p->row_starts[q];
+  }
+  const std::vector<int64_t> koff = prefix(pack_rows);
+  if (koff.back() >= INT32_MAX) return fail(HX_ERR_UNSUPPORTED, "pack-transpose key space beyond 2^31");
   std::vector<int64_t> bt_off((size_t)R + 1, 0);
-  for (int q = 0; q < R; ++q) bt_off[q + 1] = bt_off[q] + (p->row_starts[q + 1] - p->row_starts[q]) + 1;
+  for (int q = 0; q < R; ++q) bt_off[q + 1] = bt_off[q] + pack_rows[q] + 1;
   p->off[HX_F_BT_PTR] = bt_off;
   HX_TRY(p->d[HX_F_BT_PTR].alloc((size_t)bt_off.back() * 4));
   HX_TRY(p->d[HX_F_BT_PERM].alloc((size_t)E1 * 4));
   {
-    DevMem keys, gptr, gperm, bto_d;
+    DevMem keys, gptr, gperm, bto_d, koff_d;
     HX_TRY(keys.alloc((size_t)E1 * 4));
-    HX_TRY(gptr.alloc((size_t)(n + 1) * 4));
+    HX_TRY(gptr.alloc((size_t)(koff.back() + 1) * 4));
     HX_TRY(gperm.alloc((size_t)E1 * 4));
     HX_TRY(upload_vec(bto_d, bt_off));
+    HX_TRY(upload_vec(koff_d, koff));
     if (E1 > 0) {
       hipLaunchKernelGGL(k_pack_keys, dim3(blocks_for(E1)), dim3(TB), 0, s, p->d[HX_F_S1_IDX].as<int32_t>(), E1,
-                         s1o_d.as<int64_t>(), p->row_starts_d.as<int64_t>(), R, keys.as<int32_t>());
+                         s1o_d.as<int64_t>(), koff_d.as<int64_t>(), R, keys.as<int32_t>());
       HX_HIP(hipGetLastError());
     }
-    HX_TRY(dev_group_by_key(keys.as<int32_t>(), E1, n, gptr.as<int32_t>(), gperm.as<int32_t>(), s));
+    HX_TRY(dev_check_range(keys.as<int32_t>(), E1, koff.back(), "pack rows", s));
+    HX_TRY(dev_group_by_key(keys.as<int32_t>(), E1, koff.back(), gptr.as<int32_t>(), gperm.as<int32_t>(), s));
     hipLaunchKernelGGL(k_local_bt_ptr, dim3(blocks_for(bt_off.back())), dim3(TB), 0, s, gptr.as<int32_t>(),
-                       bto_d.as<int64_t>(), p->row_starts_d.as<int64_t>(), s1o_d.as<int64_t>(), R, bt_off.back(),
+                       bto_d.as<int64_t>(), koff_d.as<int64_t>(), s1o_d.as<int64_t>(), R, bt_off.back(),
                        p->d[HX_F_BT_PTR].as<int32_t>());
     HX_HIP(hipGetLastError());
     if (E1 > 0) {
@@ -876,7 +933,8 @@ int plan_common_checks(int nranks, const int64_t* row_starts, int ppn, hx_varian
   *out = nullptr;
   if (nranks <= 0 || !row_starts) return fail(HX_ERR_ARG, "bad nranks / row_starts");
   if (nranks > HX_PLAN_MAX_RANKS) return fail(HX_ERR_UNSUPPORTED, "more than %d ranks", HX_PLAN_MAX_RANKS);
-  if (variant != HX_PLAIN && variant != HX_LOCALITY_2STEP) return fail(HX_ERR_ARG, "bad variant");
+  if (variant != HX_PLAIN && variant != HX_LOCALITY_2STEP && variant != HX_LOCALITY_3STEP)
+    return fail(HX_ERR_ARG, "bad variant");
   if (ppn < 1) return fail(HX_ERR_ARG, "ppn must be >= 1");
   if (row_starts[0] != 0) return fail(HX_ERR_ARG, "row_starts[0] must be 0");
   for (int r = 0; r < nranks; ++r)

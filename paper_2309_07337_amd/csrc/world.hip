@@ -319,6 +319,8 @@ extern "C" int hx_req_from_plan(const hx_plan* p, int rank, const void* x_local,
   if (rank < 0 || rank >= p->R) return fail(HX_ERR_RANGE, "rank out of range");
   if (dtype != HX_F32 && dtype != HX_F64) return fail(HX_ERR_ARG, "bad dtype");
   if (ncols <= 0) return fail(HX_ERR_ARG, "ncols must be positive");
+  if (p->variant == HX_LOCALITY_3STEP)
+    return fail(HX_ERR_UNSUPPORTED, "3-step plans pack node-mates' rows: use a whole-decomposition batch");
   std::unique_ptr<hx_req> r(new (std::nothrow) hx_req);
   if (!r) return fail(HX_ERR_NOMEM, "out of host memory");
   r->dtype = dtype;
@@ -431,13 +433,27 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
   HX_TRY(err.alloc(4));
   HX_HIP(hipMemset(err.p, 0, 4));
 
-  // pack: x_global rows
+  // pack: x_global rows (pack indices count from the rank's first row, or
+  // from its node's first row for the 3-step plan)
+  const bool v3 = p->variant == HX_LOCALITY_3STEP;
+  std::vector<int64_t> pbase((size_t)R + 1, 0);
+  for (int r = 0; r <= R; ++r) pbase[r] = v3 && r < R ? b->row_starts[(r / p->ppn) * p->ppn] : b->row_starts[r];
+  DevMem pbase_d;
+  HX_TRY(upload_vec(pbase_d, pbase));
   HX_TRY(b->gidx_pack.alloc((size_t)b->E1_tot * 4));
   if (b->E1_tot)
     hipLaunchKernelGGL(k_add_rank_base, dim3(blocks_for(b->E1_tot)), dim3(TB), 0, s, p->d[HX_F_S1_IDX].as<int32_t>(),
-                       b->E1_tot, s1o.as<int64_t>(), R, rs_d.as<int64_t>(), b->gidx_pack.as<int32_t>());
+                       b->E1_tot, s1o.as<int64_t>(), R, pbase_d.as<int64_t>(), b->gidx_pack.as<int32_t>());
+  HX_HIP(hipGetLastError());
   // push form of the pack: global row -> send_all rows (ascending)
-  {
+  if (v3) {
+    // senders other than the owner: group the global pack map directly
+    HX_TRY(dev_check_range(b->gidx_pack.as<int32_t>(), b->E1_tot, b->n, "pack map", s));
+    HX_TRY(b->wp_ptr.alloc((size_t)(b->n + 1) * 4));
+    HX_TRY(b->wp_idx.alloc((size_t)std::max<int64_t>(b->E1_tot, 1) * 4));
+    HX_TRY(dev_group_by_key(b->gidx_pack.as<int32_t>(), b->E1_tot, b->n, b->wp_ptr.as<int32_t>(),
+                            b->wp_idx.as<int32_t>(), s));
+  } else {
     DevMem bto;
     HX_TRY(upload_vec(bto, p->off[HX_F_BT_PTR]));
     HX_TRY(b->wp_ptr.alloc((size_t)(b->n + 1) * 4));

@@ -33,7 +33,7 @@ def host(t) -> np.ndarray:
 
 
 def variant_id(v: str) -> int:
-    return P.HX_PLAIN if v == "plain" else P.HX_LOCALITY_2STEP
+    return {"plain": P.HX_PLAIN, "locality": P.HX_LOCALITY_2STEP, "locality3": P.HX_LOCALITY_3STEP}[v]
 
 
 def gpu_plan(rs, rp, cols, ppn, variant):

@@ -22,7 +22,7 @@ def exchange_for(rs, rp, cols, ppn, variant, ncols):
     return HaloExchange(plan, int(rs[-1]), H, ncols, dtype=torch.float32), plan
 
 
-@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("variant", ["plain", "locality", "locality3"])
 @pytest.mark.parametrize("case", CASES[:6])
 def test_backward_tiny_bit_exact(case, variant):
     need_gpu()
@@ -193,7 +193,7 @@ def staged_exchange(rs, rp, cols, ppn, variant, ncols, dtype, sim=True):
     return HaloExchange(plan, int(rs[-1]), H, ncols, dtype=dtype, sim_transfer=sim, staged_backward=True), plan
 
 
-@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("variant", ["plain", "locality", "locality3"])
 @pytest.mark.parametrize("case", CASES)
 def test_staged_backward_tiny_bit_exact(case, variant):
     """Backward through the plan's stages == the oracle's staged adjoint, bit

@@ -1,8 +1,9 @@
 """GPU plan kernels vs the oracle, element for element (integer arrays: bit-exact).
 
 Covers halo discovery, owner segmentation (receive lists), the send-list
-transpose, the 2-step locality lists (node dedup, stage-1 aggregated
-messages, redistribution lists, unpack map) and the transpose of the pack map.
+transpose, the 2-step and 3-step locality lists (node dedup, stage-1
+aggregated messages, redistribution lists, unpack map) and the transpose of
+the pack map.
 """
 import numpy as np
 import pytest
@@ -10,14 +11,14 @@ import pytest
 import paper_2309_07337_amd as P
 from oracle import plan as OP
 from tests.conftest import cached_grid2d, cached_grid3d, cached_random_rows
-from tests.gpu_util import assert_plan_equal, dev, gpu_plan, need_gpu, plan_rank, say
+from tests.gpu_util import assert_plan_equal, dev, gpu_plan, need_gpu, plan_rank, say, variant_id
 from tests.test_oracle_brute import CASES
 from workloads import random_small_csr
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("variant", ["plain", "locality", "locality3"])
 @pytest.mark.parametrize("case", CASES)
 def test_tiny_decompositions(case, variant):
     need_gpu()
@@ -43,7 +44,7 @@ def test_more_random_shapes(seed):
                                     bool(seed % 2))
     halos = OP.all_halos(rp, cols, rs)
     D = OP.Decomposition(halos, rs, ppn)
-    for variant in ("plain", "locality"):
+    for variant in ("plain", "locality", "locality3"):
         plan = gpu_plan(rs, rp, cols, ppn, variant)
         for r in range(R):
             assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"{variant} rank {r}")
@@ -54,7 +55,7 @@ def test_grid2d_all_ranks():
     rs, rp, cols = cached_grid2d()
     halos = OP.all_halos(rp, cols, rs)
     D = OP.Decomposition(halos, rs, 4)
-    for variant in ("plain", "locality"):
+    for variant in ("plain", "locality", "locality3"):
         say("plan grid2d", variant)
         plan = gpu_plan(rs, rp, cols, 4, variant)
         for r in range(16):
@@ -66,7 +67,7 @@ def test_grid3d_all_ranks():
     rs, rp, cols = cached_grid3d()
     halos = OP.all_halos(rp, cols, rs)
     D = OP.Decomposition(halos, rs, 64)
-    for variant in ("plain", "locality"):
+    for variant in ("plain", "locality", "locality3"):
         say("plan grid3d", variant)
         plan = gpu_plan(rs, rp, cols, 64, variant)
         for r in range(512):
@@ -80,8 +81,8 @@ def test_random_rows_sampled_ranks():
     rs, rp, cols = cached_random_rows()
     halos = OP.all_halos(rp, cols, rs)
     D = OP.Decomposition(halos, rs, 128)
-    sample = [0, 1, 127, 128, 1511, 2048, 3001, 4095]
-    for variant in ("plain", "locality"):
+    sample = [0, 1, 31, 127, 128, 1511, 2048, 3001, 4095]
+    for variant in ("plain", "locality", "locality3"):
         say("plan random_rows", variant)
         plan = gpu_plan(rs, rp, cols, 128, variant)
         for r in sample:
@@ -94,11 +95,11 @@ def test_random_rows_sampled_ranks():
 def test_from_halos_matches_from_csr_and_validates():
     need_gpu()
     rs, rp, cols = random_small_csr(300, 12, 6, 0.5, 77, False)
-    for variant in ("plain", "locality"):
+    for variant in ("plain", "locality", "locality3"):
         a = gpu_plan(rs, rp, cols, 3, variant)
         hs = [P.hx_plan_field(a, r, "halo") for r in range(12)]
         hp = np.concatenate([[0], np.cumsum([h.size for h in hs])])
-        b = P.hx_plan_from_halos(12, rs, 3, 1 if variant == "locality" else 0, hp,
+        b = P.hx_plan_from_halos(12, rs, 3, variant_id(variant), hp,
                                  dev(np.concatenate(hs).astype(np.int32)))
         for r in range(12):
             assert_plan_equal(plan_rank(b, r), plan_rank(a, r), f"rank {r}")

@@ -68,7 +68,7 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
         b.free()
 
 
-@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("variant", ["plain", "locality", "locality3"])
 @pytest.mark.parametrize("case", CASES)
 def test_world_tiny(case, variant):
     need_gpu()
@@ -87,7 +87,7 @@ def test_world_grid2d(variant):
     check_world_against_oracle(rs, rp, cols, 4, variant, 1, "f64")
 
 
-@pytest.mark.parametrize("variant", ["plain", "locality"])
+@pytest.mark.parametrize("variant", ["plain", "locality", "locality3"])
 def test_world_grid3d(variant):
     need_gpu()
     say("world grid3d", variant)
@@ -96,22 +96,32 @@ def test_world_grid3d(variant):
     check_world_against_oracle(rs, rp, cols, 64, variant, 8, "f32", full_stages=False)
 
 
-@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
-def test_world_random_rows_full_size(dtype_name):
-    """4096 ranks, locality-aware: every halo equals the direct gather x[N_r]."""
+@pytest.mark.parametrize("dtype_name,variant", [("f64", "locality"), ("f32", "locality"),
+                                                ("f64", "locality3")])
+def test_world_random_rows_full_size(dtype_name, variant):
+    """4096 ranks, locality-aware (2-step, 3-step): every halo equals the
+    direct gather x[N_r]."""
     need_gpu()
     import torch
-    say("world random_rows", dtype_name)
+    say("world random_rows", dtype_name, variant)
     rs, rp, cols = cached_random_rows()
     halos = OP.all_halos(rp, cols, rs)
     n = int(rs[-1])
     xh = uniform_pm1(7337, n).reshape(n, 1)
     if dtype_name == "f32":
         xh = xh.astype(np.float32)
-    plan = gpu_plan(rs, rp, cols, 128, "locality")
+    plan = gpu_plan(rs, rp, cols, 128, variant)
     H = sum(h.size for h in halos)
     b, halo = run_world(plan, dev(xh), H)
     assert bits_equal(host(halo), xh[np.concatenate(halos)])
+    if variant == "locality3":   # one stage-1 message per node pair that needs one
+        inter = 0
+        for r in range(4096):
+            procs = P.hx_plan_field(plan, r, "s1_procs")
+            inter += int(np.sum(procs // 128 != r // 128))
+        assert inter == 32 * 31
+        with pytest.raises(P.HXError):
+            P.hx_req_from_plan(plan, 0, dev(xh[:1024]), torch.empty(1, 1, device="cuda", dtype=halo.dtype))
 
 
 @pytest.mark.parametrize("variant", ["plain", "locality"])
