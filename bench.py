@@ -8,9 +8,10 @@ the backward of the pack (fixed-order transpose sum), each phase one
 persistent kernel replayed from a hipGraph.  The same work as one launch per
 plan per phase ("plain") is timed beside it.
 
-Other workloads (``--workload``): random_rows / random_rows_f32 (2^22 x 32
-random matrix, 4096 ranks, locality-aware plan, every rank batched, one FP64
-/ FP32 column; forward step, the staged backward reported aside), grid3d
+Other workloads (``--workload``): random_rows / random_rows_f32 /
+random_rows_3step (2^22 x 32 random matrix, 4096 ranks, 2-step or 3-step
+locality-aware plan, every rank batched, one FP64 / FP32 column; forward
+step, the staged backward reported aside), grid3d
 (27-point 128^3, 512 ranks), grid2d (5-point 512^2, 16 ranks), diff64
 (random-matrix plain plan, 64 FP32 features, forward + backward), copy (the
 1 GiB calibration copy for the PMC scale factors).
@@ -150,7 +151,7 @@ def setup_world(args, torch, P, name):
     import numpy as np
     from workloads import equal_row_starts, grid2d_5pt, grid3d_27pt, random_rows, uniform_pm1, uniform_pm1_f32
     t0 = time.time()
-    if name in ("random_rows", "random_rows_f32", "diff64"):
+    if name in ("random_rows", "random_rows_f32", "random_rows_3step", "diff64"):
         rp, cols = random_rows()
         rs, ppn = equal_row_starts(1 << 22, 4096), 128
     elif name == "grid3d":
@@ -160,7 +161,8 @@ def setup_world(args, torch, P, name):
         rp, cols = grid2d_5pt()
         rs, ppn = equal_row_starts(512 * 512, 16), 4
     log(f"generated {name} structure in {time.time() - t0:.1f}s")
-    variant = P.HX_PLAIN if name == "diff64" else P.HX_LOCALITY_2STEP
+    variant = P.HX_PLAIN if name == "diff64" else (P.HX_LOCALITY_3STEP if name.endswith("3step")
+                                                    else P.HX_LOCALITY_2STEP)
     rp_d, cols_d = torch.from_numpy(rp).cuda(), torch.from_numpy(cols).cuda()
     torch.cuda.synchronize()
     t0 = time.time()
@@ -202,11 +204,17 @@ def setup_world(args, torch, P, name):
                                        "2-step, all ranks batched, 1 x FP64",
                         "random_rows_f32": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality "
                                            "2-step, all ranks batched, 1 x FP32",
+                        "random_rows_3step": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality "
+                                             "3-step (one message per node pair), all ranks batched, 1 x FP64",
                         "grid3d": "27-point 128^3, 512 ranks, 64/node, locality 2-step, all ranks, 1 x FP64",
                         "grid2d": "5-point 512^2, 16 ranks, 4/node, locality 2-step, all ranks, 1 x FP64",
                         "diff64": "random 2^22 x 32, 4096 ranks, plain plan, 64 x FP32 features, forward "
                                   "halo gather + fixed-order transpose-sum backward"}[name],
-           "ranks": R, "halo_rows": H, "ncols": C, "plan_init_s": round(plan_s, 4)}
+           "ranks": R, "halo_rows": H, "ncols": C, "plan_init_s": round(plan_s, 4),
+           "internode_messages": int(sum(int(np.sum(P.hx_plan_field(plan, r, "s1_procs") // ppn != r // ppn))
+                                         for r in range(R))),
+           "internode_rows": int(sum(int(np.sum(P.hx_plan_field(plan, r, "s1_counts")[
+               P.hx_plan_field(plan, r, "s1_procs") // ppn != r // ppn])) for r in range(R)))}
     # the differentiation workload times forward + backward; the others are
     # forward (pack / redistribution / unpack) workloads, backward reported aside
     phases = (0, 1, 2, 3) if name == "diff64" else (0, 1, 2)
@@ -318,7 +326,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched256",
-                    choices=["batched256", "random_rows", "random_rows_f32", "grid3d", "grid2d", "diff64", "copy"])
+                    choices=["batched256", "random_rows", "random_rows_f32", "random_rows_3step", "grid3d", "grid2d",
+                             "diff64", "copy"])
     ap.add_argument("--plans", type=int, default=256)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
