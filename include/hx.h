@@ -81,7 +81,9 @@ typedef struct hx_batch hx_batch;
  * (tiles never straddle neighbors); 0 tiles each member's rows flat. */
 typedef struct {
   int tile_rows;      /* rows per tile (work unit of one workgroup iteration) */
-  int block_threads;  /* 256 or 512 */
+  int block_threads;  /* 256 or 512; 1024 is taken by the segmented sums
+                         (backward) only, which then read no LDS term
+                         windows; the gathers run it as 512 */
   int blocks_per_cu;  /* persistent grid = blocks_per_cu * #CUs */
   int nontemporal;    /* 1: streaming (non-temporal) loads/stores of index and output */
   int per_neighbor;   /* see above */

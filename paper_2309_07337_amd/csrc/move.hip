@@ -72,8 +72,9 @@ int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
   if (t->sched.tile_rows <= 0 || t->sched.block_threads <= 0 || t->sched.blocks_per_cu <= 0)
     return fail(HX_ERR_ARG, "invalid schedule (tile_rows %d, block_threads %d, blocks_per_cu %d)",
                 t->sched.tile_rows, t->sched.block_threads, t->sched.blocks_per_cu);
-  if (t->sched.block_threads != 256 && t->sched.block_threads != 512)
-    return fail(HX_ERR_ARG, "block_threads must be 256 or 512");
+  if (t->sched.block_threads != 256 && t->sched.block_threads != 512 &&
+      !(kind == KIND_SEGSUM && t->sched.block_threads == 1024))
+    return fail(HX_ERR_ARG, "block_threads must be 256 or 512 (1024: segmented sums only)");
   // keep only jobs with rows; tile prefix
   std::vector<J> kept;
   std::vector<int64_t> ts(1, 0);
@@ -156,7 +157,8 @@ int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_by
   std::vector<SegSumJob> w(jobs);
   const int64_t cap = std::min<int64_t>(kSegWinBytes, device_lds_per_block() - (8 << 10));
   int64_t win_bytes = 0;
-  bool all = s.lds_window != 0;
+  // (the windowed kernel is bounded to 512 lanes)
+  bool all = s.lds_window != 0 && s.block_threads <= 512;
   for (const auto& j : w) {
     if (j.nrows <= 0) continue;
     const int64_t bytes = j.win_rows * (int64_t)row_bytes;

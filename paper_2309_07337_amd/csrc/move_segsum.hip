@@ -10,7 +10,7 @@ namespace {
 
 #define HX_SEGSUM_KERNEL(NAME)                                                                       \
   template <class T, int VB, int NV, int LPR, int U, bool NT>                                        \
-  __global__ void __launch_bounds__(512)                                                             \
+  __global__ void __launch_bounds__(1024)                                                            \
       NAME(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs,            \
            int64_t ntiles, int tile_rows, int nv_rt) {                                               \
     segsum_body<T, VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt);                   \

@@ -113,7 +113,9 @@ Sched default_sched(int kind, int row_bytes) {
   // rows in flight per lane: 4, except for rows of 16 bytes or less, whose
   // gathers measure best with 1 (more lanes, not more rows per lane)
   s.unroll = row_bytes <= 16 && kind == KIND_GATHER ? 1 : 4;
-  if (kind == KIND_SEGSUM) s.block_threads = 512;
+  // segmented sums: 512 lanes, 1024 for rows of 64 B and more (more terms in
+  // flight per chunk; such rows read no term windows by default)
+  if (kind == KIND_SEGSUM) s.block_threads = row_bytes >= 64 ? 1024 : 512;
   // rows of 64 B and more: push by default (on gfx950 scattered full-line
   // writes run as fast as scattered reads, and the push form reads each
   // source row once instead of once per slot); short rows: pull
@@ -128,6 +130,7 @@ Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
   if (!p) return s;
   if (p->tile_rows > 0) s.tile_rows = p->tile_rows;
   if (p->block_threads > 0) s.block_threads = p->block_threads;
+  if (s.block_threads == 1024 && kind != KIND_SEGSUM) s.block_threads = 512;
   if (p->blocks_per_cu > 0) s.blocks_per_cu = p->blocks_per_cu;
   s.nontemporal = p->nontemporal ? 1 : 0;
   s.per_neighbor = p->per_neighbor ? 1 : 0;
@@ -972,8 +975,9 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     {
       const Sched s1 = best;
       for (int bpc : {2, 4, 8})
-        for (int bt : {256, 512})
+        for (int bt : {256, 512, 1024})
           for (int nt : {0, 1}) {
+            if (bt == 1024 && ph != PH_BWD) continue;  // segmented sums only
             Sched c = s1;
             c.blocks_per_cu = bpc;
             c.block_threads = bt;

@@ -60,7 +60,10 @@ SCHEDS = [None,
           dict(tile_rows=2048, block_threads=256, blocks_per_cu=2, unroll=2, push_pack=1),
           dict(tile_rows=50, block_threads=512, blocks_per_cu=2, unroll=2, push_pack=2, lds_window=1),
           dict(tile_rows=3000, unroll=4, push_pack=2, lds_window=1, per_neighbor=1),
-          dict(tile_rows=256, push_pack=2, lds_window=2)]
+          dict(tile_rows=256, push_pack=2, lds_window=2),
+          # 1024 lanes: segmented sums only (gathers run 512, term windows off)
+          dict(tile_rows=512, block_threads=1024, blocks_per_cu=8, unroll=4, nontemporal=1),
+          dict(tile_rows=100, block_threads=1024, blocks_per_cu=2, unroll=2, lds_window=1, per_neighbor=1)]
 
 
 @pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f32", 1), ("f64", 1), ("f32", 64)])
