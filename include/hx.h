@@ -84,7 +84,12 @@ typedef struct {
   int block_threads;  /* 256 or 512; 1024 is taken by the segmented sums
                          (backward) only, which then read no LDS term
                          windows; the gathers run it as 512 */
-  int blocks_per_cu;  /* persistent grid = blocks_per_cu * #CUs */
+  int blocks_per_cu;  /* grid = blocks_per_cu * #CUs workgroups, each walking
+                         a contiguous range of tiles, but never more than
+                         the tile count (rounded up to 8): a value of at
+                         least tiles / #CUs (1 << 20 is the library's) gives
+                         one workgroup per tile, dispatched by the hardware
+                         in tile order */
   int nontemporal;    /* 1: streaming (non-temporal) loads/stores of index and output */
   int per_neighbor;   /* see above */
   int unroll;         /* rows per lane in flight: 1, 2 or 4 (0 = default) */

@@ -119,10 +119,17 @@ Sched default_sched(int kind, int row_bytes);
 // LDS staging in the CSR-driven kernels (push pack, segmented sum): tiles of
 // at most kStageRows rows stage their row pointers, and their entry indices
 // when there are at most kStageEntries; the segmented sum gathers the terms
-// of consecutive rows into kSegValueBytes of LDS before adding them.
+// of consecutive rows into at most kSegValueBytes of LDS before adding them.
 constexpr int kStageRows = 512;
 constexpr int kStageEntries = 2048;
 constexpr int kSegValueBytes = 65536;
+// blocks_per_cu of a one-shot grid: the grid never exceeds the tile count
+// (rounded up to 8), so this gives one workgroup per tile, dispatched by the
+// hardware in tile order.  On gfx950 that keeps the rows in flight in a
+// compact moving window of memory and balances uneven tiles, which measures
+// 5-15 % faster than a persistent grid walking per-workgroup tile ranges
+// for streaming gathers, scatters and copies of 64 B rows and more.
+constexpr int kOneShotBpc = 1 << 20;
 // Largest source window a gather stages in LDS (larger ones read global
 // memory): two such workgroups fit in the 160 KiB of a gfx950 CU.
 constexpr int kWinBytes = 80 << 10;
@@ -142,6 +149,7 @@ struct LaunchTable {
   int row_bytes = 0;
   int vec_bytes = 0;  // 16, 8 or 4: divides row_bytes and all base pointers
   int win_bytes = 0;  // dynamic LDS of a gather table whose jobs use windows
+  int val_bytes = 0;  // segmented sums: dynamic LDS term buffer (whole rows)
   Sched sched;
   int njobs = 0;
   int64_t ntiles = 0;

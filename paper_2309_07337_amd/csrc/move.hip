@@ -178,6 +178,10 @@ int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_by
                                            : j.in2 + (j.win_lo - j.split) * (int64_t)row_bytes);
   HX_TRY(build_table(w, KIND_SEGSUM, dtype, row_bytes, s, t, a));
   t->win_bytes = t->ntiles > 0 ? (int)win_bytes : 0;
+  // term buffer: about two terms per tile row, at least 4 KiB and at most
+  // kSegValueBytes, whole rows (small tiles leave LDS for more workgroups)
+  int64_t vb = std::min<int64_t>(kSegValueBytes, std::max<int64_t>(4096, 2 * (int64_t)s.tile_rows * row_bytes));
+  t->val_bytes = t->ntiles > 0 && row_bytes > 0 ? (int)(vb / row_bytes * row_bytes) : 0;
   return HX_SUCCESS;
 }
 

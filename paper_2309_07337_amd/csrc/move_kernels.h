@@ -243,11 +243,10 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
 // Staged tiles run entry-parallel (LPR lanes per slot, U slots per lane);
 // other tiles row-parallel.  Job fields: in = source rows, out = slots.
 // ---------------------------------------------------------------------------
-// LDS staging limits (kStageRows, kStageEntries, kSegValueBytes) are declared
-// with the schedules in common.h, where the default tile sizes use them.
+// LDS staging limits (kStageRows, kStageEntries) are declared with the
+// schedules in common.h, where the default tile sizes use them.
 constexpr int STAGE_ROWS = kStageRows;
 constexpr int STAGE_ENTRIES = kStageEntries;
-constexpr int SEG_VALUE_BYTES = kSegValueBytes;
 
 template <int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
@@ -413,7 +412,8 @@ __device__ __forceinline__ const char* term_row(const char* in, const char* in2,
 
 template <class T, int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
-                                            int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
+                                            int njobs, int64_t ntiles, int tile_rows, int nv_rt,
+                                            int cap_terms) {
   using V = typename NumVec<T, VB>::type;
   const int nv = NV > 0 ? NV : nv_rt;
   constexpr int NVPL = NV > 0 ? (NV + LPR - 1) / LPR : 1;
@@ -422,8 +422,13 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
   const int rows_per_pass = blockDim.x / LPR;
   __shared__ int32_t s_ptr[STAGE_ROWS + 1];
   __shared__ int32_t s_idx[STAGE_ENTRIES];
-  __shared__ V s_val[NV > 0 ? SEG_VALUE_BYTES / VB : 1];
-  const bool stage_ptr = NV > 0 && tile_rows <= STAGE_ROWS;
+  // term buffer: dynamic LDS of cap_terms rows (sized per launch table, so
+  // small tiles leave room for more workgroups per CU)
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  V* const s_val = reinterpret_cast<V*>(s_dyn);
+  // without a term buffer the tile runs row-parallel straight from global
+  // memory (no staging, no barriers)
+  const bool stage_ptr = NV > 0 && tile_rows <= STAGE_ROWS && cap_terms > 0;
   int64_t t0, t1;
   tile_range(ntiles, &t0, &t1);
   if (t0 >= t1) return;
@@ -456,12 +461,12 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
           for (int i = threadIdx.x; i < ne; i += blockDim.x) s_idx[i] = ldv<int32_t, NT>(idx + P0 + i);
         __syncthreads();
       }
-      if (stage_idx) {
+      if (stage_idx && cap_terms > 0) {
         // Chunks of consecutive rows whose terms fit in s_val: the terms are
         // loaded entry-parallel (U per lane, all in flight together, whatever
         // the segment lengths), then every row adds its own terms from LDS in
         // entry order and stores the sum.
-        constexpr int CAP = SEG_VALUE_BYTES / (NV * VB);  // terms per chunk
+        const int CAP = cap_terms;  // terms per chunk
         int ra = 0;
         while (ra < nt) {
           int lo = ra, hi = nt;  // last row boundary whose terms still fit
@@ -536,39 +541,27 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
         }
         continue;
       }
-      // row-parallel fallback (tiles whose entries were not staged): one
-      // term of UR rows per lane in flight, the terms of a row in order
-      constexpr int UR = 1;
-      for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * UR) {
-        int32_t a[UR], len[UR];
-        int maxlen = 0;
-#pragma unroll
-        for (int u = 0; u < UR; ++u) {
-          const int64_t r = base + (int64_t)u * rows_per_pass;
-          a[u] = 0;
-          len[u] = -1;
-          if (r < r1) {
-            if (stage_ptr) {
-              a[u] = s_ptr[r - r0];
-              len[u] = s_ptr[r - r0 + 1] - a[u];
-            } else {
-              a[u] = ptr[r];
-              len[u] = ptr[r + 1] - a[u];
-            }
-          }
-          maxlen = max(maxlen, len[u]);
+      // row-parallel (no term buffer, or tiles whose entries were not
+      // staged): one row per lane group, up to U of its terms in flight,
+      // added in order
+      for (int64_t r = r0 + rsub; r < r1; r += rows_per_pass) {
+        int32_t a, len;
+        if (stage_ptr) {
+          a = s_ptr[r - r0];
+          len = s_ptr[r - r0 + 1] - a;
+        } else {
+          a = ptr[r];
+          len = ptr[r + 1] - a;
         }
-        V acc[UR][NVPL];
+        V acc[NVPL];
 #pragma unroll
-        for (int u = 0; u < UR; ++u)
+        for (int k = 0; k < NVPL; ++k) acc[k] = (V)(T)0;
+        for (int32_t d0 = 0; d0 < len; d0 += U) {
+          V v[U][NVPL];
 #pragma unroll
-          for (int k = 0; k < NVPL; ++k) acc[u][k] = (V)(T)0;
-        for (int d = 0; d < maxlen; ++d) {
-          V v[UR][NVPL];
-#pragma unroll
-          for (int u = 0; u < UR; ++u) {
-            if (d < len[u]) {
-              const int32_t e = a[u] + d;
+          for (int u = 0; u < U; ++u) {
+            if (d0 + u < len) {
+              const int32_t e = a + d0 + u;
               const int32_t src = stage_idx ? s_idx[e - P0] : ldv<int32_t, NT>(idx + e);
               const V* sp = reinterpret_cast<const V*>(term_row(in, in2, split, src, rb));
 #pragma unroll
@@ -579,23 +572,18 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
             }
           }
 #pragma unroll
-          for (int u = 0; u < UR; ++u) {
-            if (d < len[u]) {
+          for (int u = 0; u < U; ++u) {
+            if (d0 + u < len) {
 #pragma unroll
-              for (int k = 0; k < NVPL; ++k) acc[u][k] = (d == 0) ? v[u][k] : acc[u][k] + v[u][k];
+              for (int k = 0; k < NVPL; ++k) acc[k] = (d0 + u == 0) ? v[u][k] : acc[k] + v[u][k];
             }
           }
         }
+        V* dp = reinterpret_cast<V*>(out + r * (int64_t)rb);
 #pragma unroll
-        for (int u = 0; u < UR; ++u) {
-          if (len[u] >= 0) {
-            V* dp = reinterpret_cast<V*>(out + (base + (int64_t)u * rows_per_pass) * rb);
-#pragma unroll
-            for (int k = 0; k < NVPL; ++k) {
-              const int vi = lane_v + k * LPR;
-              if (NV % LPR == 0 || vi < NV) stv<V, NT>(dp + vi, acc[u][k]);
-            }
-          }
+        for (int k = 0; k < NVPL; ++k) {
+          const int vi = lane_v + k * LPR;
+          if (NV % LPR == 0 || vi < NV) stv<V, NT>(dp + vi, acc[k]);
         }
       }
       if (stage_ptr) __syncthreads();  // the next tile overwrites the staged indices

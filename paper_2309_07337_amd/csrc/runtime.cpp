@@ -122,6 +122,14 @@ Sched default_sched(int kind, int row_bytes) {
   s.push_pack = kind == KIND_GATHER && row_bytes >= 64 ? 1 : 0;
   // short rows: gathers and segmented sums read their jobs' windows from LDS
   s.lds_window = row_bytes <= 16 ? 1 : 0;
+  // gathers without windows: one workgroup per tile (a window would be
+  // staged again by every workgroup); segmented sums of rows of 64 B and
+  // more: the same, two terms per lane in flight
+  if (kind == KIND_GATHER && !s.lds_window) s.blocks_per_cu = kOneShotBpc;
+  if (kind == KIND_SEGSUM && row_bytes >= 64) {
+    s.blocks_per_cu = kOneShotBpc;
+    s.unroll = 2;
+  }
   return s;
 }
 
@@ -974,7 +982,7 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     tile_stage();
     {
       const Sched s1 = best;
-      for (int bpc : {2, 4, 8})
+      for (int bpc : {2, 4, 8, kOneShotBpc})
         for (int bt : {256, 512, 1024})
           for (int nt : {0, 1}) {
             if (bt == 1024 && ph != PH_BWD) continue;  // segmented sums only

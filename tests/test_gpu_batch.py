@@ -63,7 +63,11 @@ SCHEDS = [None,
           dict(tile_rows=256, push_pack=2, lds_window=2),
           # 1024 lanes: segmented sums only (gathers run 512, term windows off)
           dict(tile_rows=512, block_threads=1024, blocks_per_cu=8, unroll=4, nontemporal=1),
-          dict(tile_rows=100, block_threads=1024, blocks_per_cu=2, unroll=2, lds_window=1, per_neighbor=1)]
+          dict(tile_rows=100, block_threads=1024, blocks_per_cu=2, unroll=2, lds_window=1, per_neighbor=1),
+          # one workgroup per tile (one-shot grid), small segmented-sum term buffers
+          dict(tile_rows=24, blocks_per_cu=1 << 20, block_threads=1024, unroll=2),
+          dict(tile_rows=300, blocks_per_cu=1 << 20, push_pack=1, unroll=4, nontemporal=1, lds_window=2),
+          dict(tile_rows=7, blocks_per_cu=1 << 20, lds_window=1, per_neighbor=1)]
 
 
 @pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f32", 1), ("f64", 1), ("f32", 64)])
@@ -139,11 +143,14 @@ def test_batch_state_machine():
 
 
 @pytest.mark.parametrize("sched", [dict(tile_rows=16, push_pack=1), dict(tile_rows=64, push_pack=1, unroll=2),
-                                   dict(tile_rows=4096, push_pack=1), dict(tile_rows=64, push_pack=2)])
+                                   dict(tile_rows=4096, push_pack=1), dict(tile_rows=64, push_pack=2),
+                                   dict(tile_rows=16, blocks_per_cu=1 << 20, block_threads=1024)])
 def test_high_fan_out(sched):
     """Every source row goes to 100 neighbors: push tiles whose entries do not
     fit the staging buffer (64 rows x 100 slots) take the row-parallel form,
-    smaller tiles the entry-parallel one; the backward sums 100 terms per row."""
+    smaller tiles the entry-parallel one; the backward sums 100 terms per row
+    (more than a 16-row tile's 4 KiB term buffer holds: such a row is summed
+    straight from global memory)."""
     need_gpu()
     import torch
     n, k, C = 90, 100, 16
