@@ -28,6 +28,25 @@ __global__ void __launch_bounds__(256) k_check_windows(const GatherJob* __restri
   }
 }
 
+// te[t] = {ptr[r0], ptr[r1]} of tile t of a segmented-sum table (its rows
+// [r0, r1) of job j), so a workgroup can load its tile's row pointers and
+// entry indices together instead of one after the other.
+__global__ void __launch_bounds__(256) k_tile_terms(const SegSumJob* __restrict__ jobs,
+                                                    const int64_t* __restrict__ ts, int njobs, int64_t ntiles,
+                                                    int tile_rows, int2* __restrict__ te) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = njobs - 1;  // largest j with ts[j] <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ts[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int64_t r0 = (t - ts[lo]) * (int64_t)tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, jobs[lo].nrows);
+    te[t] = make_int2(jobs[lo].ptr[r0], jobs[lo].ptr[r1]);
+  }
+}
+
 // Clears the windows of jobs whose indices leave them (device-side check).
 int drop_bad_windows(std::vector<GatherJob>* w) {
   std::vector<int> at;
@@ -89,6 +108,7 @@ int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
     t->grid = 0;
     t->jobs.release();
     t->tile_start.release();
+    t->tile_terms.release();
     return HX_SUCCESS;
   }
   t->vec_bytes = pick_vec(row_bytes, align_or);
@@ -182,6 +202,15 @@ int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_by
   // kSegValueBytes, whole rows (small tiles leave LDS for more workgroups)
   int64_t vb = std::min<int64_t>(kSegValueBytes, std::max<int64_t>(4096, 2 * (int64_t)s.tile_rows * row_bytes));
   t->val_bytes = t->ntiles > 0 && row_bytes > 0 ? (int)(vb / row_bytes * row_bytes) : 0;
+  // entry range of every tile (read by the staged forms)
+  if (t->ntiles > 0) {
+    HX_TRY(t->tile_terms.alloc((size_t)t->ntiles * sizeof(int2)));
+    const int grid = (int)std::min<int64_t>((t->ntiles + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_tile_terms, dim3(grid), dim3(256), 0, 0, t->jobs.as<SegSumJob>(), t->tile_start.as<int64_t>(),
+                       t->njobs, t->ntiles, t->sched.tile_rows, t->tile_terms.as<int2>());
+    HX_HIP(hipGetLastError());
+    HX_HIP(hipStreamSynchronize(0));
+  }
   return HX_SUCCESS;
 }
 

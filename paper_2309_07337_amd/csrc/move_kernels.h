@@ -412,8 +412,8 @@ __device__ __forceinline__ const char* term_row(const char* in, const char* in2,
 
 template <class T, int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
-                                            int njobs, int64_t ntiles, int tile_rows, int nv_rt,
-                                            int cap_terms) {
+                                            const int2* __restrict__ te, int njobs, int64_t ntiles,
+                                            int tile_rows, int nv_rt, int cap_terms) {
   using V = typename NumVec<T, VB>::type;
   const int nv = NV > 0 ? NV : nv_rt;
   constexpr int NVPL = NV > 0 ? (NV + LPR - 1) / LPR : 1;
@@ -447,18 +447,24 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
     const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
     const size_t rb = (size_t)nv * VB;
     if constexpr (NV > 0) {
-      // prologue: stage the tile's pointers (and entries when they fit)
+      // prologue: stage the tile's pointers and, when they fit, its entry
+      // indices, both loaded together (the tile's entry range is known)
       int32_t P0 = 0;
       bool stage_idx = false;
       const int nt = (int)(r1 - r0);
       if (stage_ptr) {
-        for (int i = threadIdx.x; i <= nt; i += blockDim.x) s_ptr[i] = ptr[r0 + i];
-        __syncthreads();
-        P0 = s_ptr[0];
-        const int32_t ne = s_ptr[nt] - P0;
+        const int2 er = te[t];
+        P0 = er.x;
+        const int32_t ne = er.y - P0;
         stage_idx = ne <= STAGE_ENTRIES;
-        if (stage_idx)
-          for (int i = threadIdx.x; i < ne; i += blockDim.x) s_idx[i] = ldv<int32_t, NT>(idx + P0 + i);
+        const int nl = max(nt + 1, stage_idx ? ne : 0);
+        for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+          int32_t pv = 0, iv = 0;
+          if (i <= nt) pv = ptr[r0 + i];
+          if (stage_idx && i < ne) iv = ldv<int32_t, NT>(idx + P0 + i);
+          if (i <= nt) s_ptr[i] = pv;
+          if (stage_idx && i < ne) s_idx[i] = iv;
+        }
         __syncthreads();
       }
       if (stage_idx && cap_terms > 0) {

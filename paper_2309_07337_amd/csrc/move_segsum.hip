@@ -12,8 +12,8 @@ namespace {
   template <class T, int VB, int NV, int LPR, int U, bool NT>                                        \
   __global__ void __launch_bounds__(1024)                                                            \
       NAME(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs,            \
-           int64_t ntiles, int tile_rows, int nv_rt, int cap_terms) {                                \
-    segsum_body<T, VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt, cap_terms);        \
+           const int2* __restrict__ te, int64_t ntiles, int tile_rows, int nv_rt, int cap_terms) {   \
+    segsum_body<T, VB, NV, LPR, U, NT>(jobs, ts, te, njobs, ntiles, tile_rows, nv_rt, cap_terms);    \
   }                                                                                                  \
   template <class T, int VB, int NV, int LPR, int U, bool NT>                                        \
   __global__ void __launch_bounds__(512)                                                             \
@@ -40,7 +40,8 @@ namespace {
         const int vb = NV > 0 ? t.val_bytes : 0; /* term buffer (fixed shapes only) */               \
         hipLaunchKernelGGL((NAME<T, VB, NV, LPR, U, NT>), dim3(t.grid), dim3(t.sched.block_threads), \
                            (unsigned)vb, s, t.jobs.as<SegSumJob>(), t.tile_start.as<int64_t>(),      \
-                           t.njobs, t.ntiles, t.sched.tile_rows, nv, vb / (NV > 0 ? NV * VB : 1));   \
+                           t.njobs, t.tile_terms.as<int2>(), t.ntiles, t.sched.tile_rows, nv,        \
+                           vb / (NV > 0 ? NV * VB : 1));                                             \
       }                                                                                              \
     }                                                                                                \
   };
