@@ -156,7 +156,7 @@ struct LaunchTable {
   int grid = 0;
   DevMem jobs;        // GatherJob[] or SegSumJob[]
   DevMem tile_start;  // int64_t[njobs + 1]
-  DevMem tile_terms;  // segmented sums: int2[ntiles], entry range {ptr[r0], ptr[r1]} of each tile
+  DevMem tile_terms;  // segmented sums, push pack: int2[ntiles], entry range {ptr[r0], ptr[r1]} of each tile
   bool empty() const { return ntiles == 0; }
 };
 

@@ -28,9 +28,9 @@ __global__ void __launch_bounds__(256) k_check_windows(const GatherJob* __restri
   }
 }
 
-// te[t] = {ptr[r0], ptr[r1]} of tile t of a segmented-sum table (its rows
-// [r0, r1) of job j), so a workgroup can load its tile's row pointers and
-// entry indices together instead of one after the other.
+// te[t] = {ptr[r0], ptr[r1]} of tile t of a segmented-sum or push table
+// (its rows [r0, r1) of job j), so a workgroup can load its tile's row
+// pointers and entry indices together instead of one after the other.
 __global__ void __launch_bounds__(256) k_tile_terms(const SegSumJob* __restrict__ jobs,
                                                     const int64_t* __restrict__ ts, int njobs, int64_t ntiles,
                                                     int tile_rows, int2* __restrict__ te) {
@@ -124,6 +124,19 @@ int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
   return HX_SUCCESS;
 }
 
+// Entry range of every tile of a CSR-driven table (segmented sum, push
+// pack), read by their staged forms.
+int fill_tile_terms(LaunchTable* t) {
+  if (t->ntiles == 0) return HX_SUCCESS;
+  HX_TRY(t->tile_terms.alloc((size_t)t->ntiles * sizeof(int2)));
+  const int grid = (int)std::min<int64_t>((t->ntiles + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_tile_terms, dim3(grid), dim3(256), 0, 0, t->jobs.as<SegSumJob>(), t->tile_start.as<int64_t>(),
+                     t->njobs, t->ntiles, t->sched.tile_rows, t->tile_terms.as<int2>());
+  HX_HIP(hipGetLastError());
+  HX_HIP(hipStreamSynchronize(0));
+  return HX_SUCCESS;
+}
+
 uintptr_t align_of(const std::vector<SegSumJob>& jobs, int row_bytes) {
   uintptr_t a = (uintptr_t)row_bytes;
   for (const auto& j : jobs) {
@@ -202,22 +215,14 @@ int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_by
   // kSegValueBytes, whole rows (small tiles leave LDS for more workgroups)
   int64_t vb = std::min<int64_t>(kSegValueBytes, std::max<int64_t>(4096, 2 * (int64_t)s.tile_rows * row_bytes));
   t->val_bytes = t->ntiles > 0 && row_bytes > 0 ? (int)(vb / row_bytes * row_bytes) : 0;
-  // entry range of every tile (read by the staged forms)
-  if (t->ntiles > 0) {
-    HX_TRY(t->tile_terms.alloc((size_t)t->ntiles * sizeof(int2)));
-    const int grid = (int)std::min<int64_t>((t->ntiles + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_tile_terms, dim3(grid), dim3(256), 0, 0, t->jobs.as<SegSumJob>(), t->tile_start.as<int64_t>(),
-                       t->njobs, t->ntiles, t->sched.tile_rows, t->tile_terms.as<int2>());
-    HX_HIP(hipGetLastError());
-    HX_HIP(hipStreamSynchronize(0));
-  }
-  return HX_SUCCESS;
+  return fill_tile_terms(t);
 }
 
 int build_scatter_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
                         LaunchTable* t, int tag) {
   t->tag = tag;
-  return build_table(jobs, KIND_SCATTER, dtype, row_bytes, s, t, align_of(jobs, row_bytes));
+  HX_TRY(build_table(jobs, KIND_SCATTER, dtype, row_bytes, s, t, align_of(jobs, row_bytes)));
+  return fill_tile_terms(t);
 }
 
 int launch_table(const LaunchTable& t, hipStream_t s) {

@@ -250,7 +250,8 @@ constexpr int STAGE_ENTRIES = kStageEntries;
 
 template <int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
-                                             int njobs, int64_t ntiles, int tile_rows, int nv_rt) {
+                                             const int2* __restrict__ te, int njobs, int64_t ntiles,
+                                             int tile_rows, int nv_rt) {
   using V = typename RawVec<VB>::type;
   const int nv = NV > 0 ? NV : nv_rt;
   constexpr int NVPL = NV > 0 ? (NV + LPR - 1) / LPR : 1;
@@ -279,20 +280,29 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
       int32_t P0 = 0, ne = 0;
       bool stage_idx = false;
       if (stage_ptr) {
+        // pointers and entry indices loaded together (the tile's entry
+        // range is known)
         const int nt = (int)(r1 - r0);
-        for (int i = threadIdx.x; i <= nt; i += blockDim.x) s_ptr[i] = ptr[r0 + i];
-        __syncthreads();
-        P0 = s_ptr[0];
-        ne = s_ptr[nt] - P0;
+        const int2 er = te[t];
+        P0 = er.x;
+        ne = er.y - P0;
         stage_idx = ne <= STAGE_ENTRIES;
+        const int nl = max(nt + 1, stage_idx ? ne : 0);
+        for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+          int32_t pv = 0, iv = 0;
+          if (i <= nt) pv = ptr[r0 + i];
+          if (stage_idx && i < ne) iv = ldv<int32_t, NT>(idx + P0 + i);
+          if (i <= nt) s_ptr[i] = pv;
+          if (stage_idx && i < ne) s_idx[i] = iv;
+        }
+        __syncthreads();
         if (stage_idx) {
-          for (int i = threadIdx.x; i < ne; i += blockDim.x) s_idx[i] = ldv<int32_t, NT>(idx + P0 + i);
           // the tile row of every entry, so the entries can be spread over
           // the lanes evenly whatever the rows' slot counts
           for (int i = threadIdx.x; i < nt; i += blockDim.x)
             for (int32_t e = s_ptr[i]; e < s_ptr[i + 1]; ++e) s_row[e - P0] = (int16_t)i;
+          __syncthreads();
         }
-        __syncthreads();
       }
       if (stage_idx) {
         // entry-parallel: LPR lanes per entry, U entries per lane; entries of
