@@ -107,6 +107,12 @@ typedef struct {
                          when the launch table is built) and gathers from
                          LDS; 2 = gather from global memory; 0 = default (1
                          for rows of 16 bytes or less, else 2) */
+  int pair_rows;      /* gathers of 8-byte rows: 1 = two rows per lane (one
+                         8-byte load of the index pair, one 16-byte store;
+                         taken where every destination is 16-byte aligned,
+                         every index list 8-byte aligned, the tile size even
+                         and no LDS window is used); 2 = one row per lane;
+                         0 = default (2) */
 } hx_sched;
 
 /* ---------------------------------------------------------------------------
@@ -301,10 +307,11 @@ int hx_req_free(hx_req** req);
  *   candidates write the same arenas/halos a start/wait would), keeps the
  *   fastest, re-captures the graphs, and records it in the tuning cache
  *   (file named by HX_TUNE_CACHE, if set).  Search per phase: tile size x
- *   rows per lane x pack form x LDS windows, then launch shape x streaming
- *   hints, then the first dimensions again; each candidate is the average of
- *   three back-to-back launches, best of two trials.  With HX_TUNE_LOG set,
- *   every candidate's time goes to stderr.
+ *   rows per lane x pack form x LDS windows x rows per lane pairing (8-byte
+ *   rows), then launch shape (persistent or one-shot grid, workgroup size) x
+ *   streaming hints, then the first dimensions again; each candidate is the
+ *   average of three back-to-back launches, best of two trials.  With
+ *   HX_TUNE_LOG set, every candidate's time goes to stderr.
  * ------------------------------------------------------------------------- */
 enum { HX_WORLD_SIM_TRANSFER = 1, HX_WORLD_STAGED_BACKWARD = 2 };
 int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, hx_batch** out);
@@ -321,7 +328,7 @@ int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out);
 int hx_batch_backward(hx_batch* b, void* stream);
 int hx_batch_backward_plain(hx_batch* b, void* stream);
 int hx_batch_tune(hx_batch* b, void* stream);
-/* hx_batch_launch_phase: launch the persistent kernel of one phase alone
+/* hx_batch_launch_phase: launch the kernel of one phase alone
  *   (0 pack, 1 redistribution, 2 unpack, 3 backward) from the same launch
  *   table the graphs replay, outside the Start/Wait state machine, so that a
  *   caller can time each kernel; the simulated transfers are not run.

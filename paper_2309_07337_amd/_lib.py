@@ -53,7 +53,7 @@ class HXError(RuntimeError):
 class hx_sched(C.Structure):
     _fields_ = [("tile_rows", C.c_int), ("block_threads", C.c_int), ("blocks_per_cu", C.c_int),
                 ("nontemporal", C.c_int), ("per_neighbor", C.c_int), ("unroll", C.c_int),
-                ("push_pack", C.c_int), ("lds_window", C.c_int)]
+                ("push_pack", C.c_int), ("lds_window", C.c_int), ("pair_rows", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

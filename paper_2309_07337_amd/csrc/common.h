@@ -113,6 +113,7 @@ struct Sched {
   int unroll = 0;     // rows per lane in flight: 2, 4, 8 (0 = 4)
   int push_pack = 0;  // pack in push form (read each source row once)
   int lds_window = 0; // gathers stage each job's source window in LDS
+  int pair_rows = 0;  // gathers of 8-byte rows: two rows per lane
 };
 Sched default_sched(int kind, int row_bytes);
 
@@ -150,6 +151,7 @@ struct LaunchTable {
   int vec_bytes = 0;  // 16, 8 or 4: divides row_bytes and all base pointers
   int win_bytes = 0;  // dynamic LDS of a gather table whose jobs use windows
   int val_bytes = 0;  // segmented sums: dynamic LDS term buffer (whole rows)
+  int pair = 0;       // gathers of 8-byte rows: two rows per lane (alignment and tile size allow it)
   Sched sched;
   int njobs = 0;
   int64_t ntiles = 0;

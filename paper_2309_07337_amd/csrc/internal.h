@@ -55,6 +55,7 @@ struct hx_plan {
 
 struct hx_batch {
   bool world = false;
+  int variant = HX_PLAIN;  // worlds: the plan's variant (part of the tuning-cache key)
   int dtype = HX_F64;
   int ncols = 1;
   size_t row_bytes = 8;

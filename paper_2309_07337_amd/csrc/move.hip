@@ -177,6 +177,12 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
   HX_TRY(build_table(w, KIND_GATHER, dtype, row_bytes, s, t, a));
   // (the runtime-row-size kernel form ignores windows and reads global memory)
   t->win_bytes = t->ntiles > 0 ? (int)win_bytes : 0;
+  // 8-byte rows two per lane: 16-byte aligned destinations, 8-byte aligned
+  // index pairs (even tile starts), no windows
+  bool pair = s.pair_rows && row_bytes == 8 && t->vec_bytes == 8 && t->win_bytes == 0 && t->sched.tile_rows % 2 == 0;
+  for (const auto& j : w)
+    if (j.nrows > 0 && (((uintptr_t)j.dst % 16) != 0 || ((uintptr_t)j.idx % 8) != 0)) pair = false;
+  t->pair = t->ntiles > 0 && pair ? 1 : 0;
   return HX_SUCCESS;
 }
 

@@ -14,9 +14,23 @@ namespace {
            int64_t ntiles, int tile_rows, int nv_rt, int use_win) {                            \
     gather_body<VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt, use_win);       \
   }                                                                                            \
+  template <int U, bool NT>                                                                    \
+  __global__ void __launch_bounds__(512)                                                       \
+      NAME##_pair(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs, \
+                  int64_t ntiles, int tile_rows) {                                             \
+    gather_pair_body<U, NT>(jobs, ts, njobs, ntiles, tile_rows);                               \
+  }                                                                                            \
   struct NAME##_go {                                                                           \
     template <int VB, int NV, int LPR, int U, bool NT>                                         \
     static void go(const LaunchTable& t, hipStream_t s, int nv) {                              \
+      if constexpr (VB == 8 && NV == 1 && LPR == 1) {                                          \
+        if (t.pair) {                                                                          \
+          hipLaunchKernelGGL((NAME##_pair<U, NT>), dim3(t.grid), dim3(t.sched.block_threads), 0, \
+                             s, t.jobs.as<GatherJob>(), t.tile_start.as<int64_t>(), t.njobs,   \
+                             t.ntiles, t.sched.tile_rows);                                     \
+          return;                                                                              \
+        }                                                                                      \
+      }                                                                                        \
       hipLaunchKernelGGL((NAME<VB, NV, LPR, U, NT>), dim3(t.grid), dim3(t.sched.block_threads), \
                          (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                     \
                          t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows, nv, \

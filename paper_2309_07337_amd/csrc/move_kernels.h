@@ -25,6 +25,7 @@ namespace kern {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -230,6 +231,76 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
         const V* sp = reinterpret_cast<const V*>(src + s * rb);
         V* dp = reinterpret_cast<V*>(dst + r * rb);
         for (int vi = lane_v; vi < nv; vi += LPR) stv<V, NT>(dp + vi, sp[vi]);
+      }
+    }
+    signal_tile(jobs[j].ready, r1 - r0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pull of 8-byte rows, two rows per lane: rows 2p and 2p + 1 of a tile take
+// one 8-byte load of their index pair, two 8-byte row loads and one 16-byte
+// store (half the index and store instructions of one row per lane; 8-byte
+// rows are bound by memory requests, not bytes).  The table builder enables
+// it only when every job's destination is 16-byte aligned, its index list
+// 8-byte aligned, the tile size even and no job uses an LDS window; a job's
+// odd last row is a half pair (one index, one 8-byte store).
+// ---------------------------------------------------------------------------
+template <int U, bool NT>
+__device__ __forceinline__ void gather_pair_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
+                                                 int njobs, int64_t ntiles, int tile_rows) {
+  using R8 = typename RawVec<8>::type;
+  using R16 = typename RawVec<16>::type;
+  int64_t t0, t1;
+  tile_range(ntiles, &t0, &t1);
+  if (t0 >= t1) return;
+  int j = find_job(ts, njobs, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= ts[j + 1]) ++j;
+    const R8* __restrict__ src = reinterpret_cast<const R8*>(jobs[j].src);
+    char* __restrict__ dst = jobs[j].dst;
+    const int32_t* __restrict__ idx = jobs[j].idx;
+    const int64_t nrows = jobs[j].nrows;
+    const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;  // even
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
+    const int64_t p0 = r0 >> 1, p1 = (r1 + 1) >> 1;  // pairs of the tile
+    for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)blockDim.x * U) {
+      int64_t s0[U], s1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // lanes past the tile's end redo its last pair (valid loads)
+        const int64_t p = min(base + (int64_t)u * blockDim.x, p1 - 1);
+        if (2 * p + 1 < r1) {
+          if (idx) {
+            const i32x2 ip = ldv<i32x2, NT>(reinterpret_cast<const i32x2*>(idx) + p);
+            s0[u] = ip.x;
+            s1[u] = ip.y;
+          } else {
+            s0[u] = 2 * p;
+            s1[u] = 2 * p + 1;
+          }
+        } else {
+          s0[u] = idx ? (int64_t)ldv<int32_t, NT>(idx + 2 * p) : 2 * p;
+          s1[u] = s0[u];
+        }
+      }
+      R8 a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a[u] = src[s0[u]];
+        b[u] = src[s1[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = base + (int64_t)u * blockDim.x;
+        if (p < p1) {
+          if (2 * p + 1 < r1) {
+            const R16 w = {a[u].x, a[u].y, b[u].x, b[u].y};
+            stv<R16, NT>(reinterpret_cast<R16*>(dst) + p, w);
+          } else {
+            stv<R8, NT>(reinterpret_cast<R8*>(dst) + 2 * p, a[u]);
+          }
+        }
       }
     }
     signal_tile(jobs[j].ready, r1 - r0);

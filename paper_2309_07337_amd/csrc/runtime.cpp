@@ -147,6 +147,8 @@ Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
   else if (p->push_pack == 2) s.push_pack = 0;
   if (p->lds_window == 1) s.lds_window = 1;
   else if (p->lds_window == 2) s.lds_window = 0;
+  if (p->pair_rows == 1) s.pair_rows = 1;
+  else if (p->pair_rows == 2) s.pair_rows = 0;
   return s;
 }
 
@@ -160,6 +162,7 @@ hx_sched to_public(const Sched& s) {
   o.unroll = s.unroll;
   o.push_pack = s.push_pack ? 1 : 2;
   o.lds_window = s.lds_window ? 1 : 2;
+  o.pair_rows = s.pair_rows ? 1 : 2;
   return o;
 }
 
@@ -663,6 +666,7 @@ static std::string cache_key(const hx_batch* b, int phase) {
   }
   k << arch_name() << "|p" << phase << "|t" << b->dtype << "|rb" << b->row_bytes << "|r" << ilog2(rows + 1)
     << "|j" << ilog2(njobs + 1) << "|w" << (b->world ? 1 : 0);
+  if (b->world) k << "|v" << b->variant;  // 2-step and 3-step worlds differ in shape
   return k.str();
 }
 
@@ -683,6 +687,7 @@ static bool cache_lookup(const std::string& key, Sched* out) {
           s.unroll >> s.push_pack))
       continue;
     if (!(ls >> s.lds_window)) s.lds_window = 0;  // lines written before the field existed
+    if (!(ls >> s.pair_rows)) s.pair_rows = 0;
     if (k == key) { *out = s; found = true; }
   }
   return found;
@@ -694,7 +699,8 @@ static void cache_store(const std::string& key, const Sched& s) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   std::ofstream f(path, std::ios::app);
   f << key << ' ' << s.tile_rows << ' ' << s.block_threads << ' ' << s.blocks_per_cu << ' ' << s.nontemporal
-    << ' ' << s.per_neighbor << ' ' << s.unroll << ' ' << s.push_pack << ' ' << s.lds_window << '\n';
+    << ' ' << s.per_neighbor << ' ' << s.unroll << ' ' << s.push_pack << ' ' << s.lds_window << ' ' << s.pair_rows
+    << '\n';
 }
 
 // Members with pack completion counters need the pull form of the pack.
@@ -950,9 +956,9 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
         ms += msf;
       }
       if (log)
-        std::fprintf(stderr, "hx tune phase %d: tile %d bt %d bpc %d nt %d unroll %d push %d win %d: %.4f ms\n", ph,
-                     c.tile_rows, c.block_threads, c.blocks_per_cu, c.nontemporal, c.unroll, c.push_pack,
-                     c.lds_window, ms);
+        std::fprintf(stderr, "hx tune phase %d: tile %d bt %d bpc %d nt %d unroll %d push %d win %d pair %d: %.4f ms\n",
+                     ph, c.tile_rows, c.block_threads, c.blocks_per_cu, c.nontemporal, c.unroll, c.push_pack,
+                     c.lds_window, c.pair_rows, ms);
       if (rc == HX_SUCCESS && ms < best_ms * 0.98f) {
         best_ms = ms;
         best = c;
@@ -960,24 +966,29 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     };
     consider(best);
     // stage 1: work per tile, rows in flight, pull vs push (pack), LDS
-    // source windows (gathers); stage 2: launch shape and streaming hints;
+    // source windows and two rows per lane (gathers); stage 2: launch shape
+    // (persistent or one-shot grid, workgroup size) and streaming hints;
     // stage 3: stage 1 again around the new launch shape
     auto tile_stage = [&]() {
       const Sched s0 = best;
       for (int tf : {1, 2, 4, 8, 16, 32})
         for (int u : {1, 2, 4})
           for (int push : {0, 1})
-            for (int win : {0, 1}) {
-              if (push && (ph != PH_PACK || batch_has_ready(b))) continue;
-              if (win && push) continue;
-              Sched c = s0;
-              c.tile_rows = std::max(16, base * tf / 8);
-              c.unroll = u;
-              c.push_pack = ph == PH_PACK ? push : s0.push_pack;
-              c.lds_window = win;
-              c.per_neighbor = 0;
-              consider(c);
-            }
+            for (int win : {0, 1})
+              for (int pair : {0, 1}) {
+                if (push && (ph != PH_PACK || batch_has_ready(b))) continue;
+                if (win && push) continue;
+                // two rows per lane: pull gathers of 8-byte rows without windows
+                if (pair && (b->row_bytes != 8 || win || push || ph == PH_BWD)) continue;
+                Sched c = s0;
+                c.tile_rows = std::max(16, base * tf / 8);
+                c.unroll = u;
+                c.push_pack = ph == PH_PACK ? push : s0.push_pack;
+                c.lds_window = win;
+                c.pair_rows = pair;
+                c.per_neighbor = 0;
+                consider(c);
+              }
     };
     tile_stage();
     {

@@ -395,6 +395,7 @@ extern "C" int hx_batch_from_plan(const hx_plan* p, const void* x_global, void* 
   std::unique_ptr<hx_batch> b(new (std::nothrow) hx_batch);
   if (!b) return fail(HX_ERR_NOMEM, "out of host memory");
   b->world = true;
+  b->variant = p->variant;
   b->dtype = dtype;
   b->ncols = ncols;
   b->row_bytes = (size_t)ncols * dtype_bytes(dtype);

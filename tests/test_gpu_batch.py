@@ -67,7 +67,11 @@ SCHEDS = [None,
           # one workgroup per tile (one-shot grid), small segmented-sum term buffers
           dict(tile_rows=24, blocks_per_cu=1 << 20, block_threads=1024, unroll=2),
           dict(tile_rows=300, blocks_per_cu=1 << 20, push_pack=1, unroll=4, nontemporal=1, lds_window=2),
-          dict(tile_rows=7, blocks_per_cu=1 << 20, lds_window=1, per_neighbor=1)]
+          dict(tile_rows=7, blocks_per_cu=1 << 20, lds_window=1, per_neighbor=1),
+          # 8-byte rows two per lane (even tiles; odd job ends are half pairs)
+          dict(tile_rows=64, blocks_per_cu=1 << 20, pair_rows=1, unroll=4),
+          dict(tile_rows=1000, pair_rows=1, unroll=2, nontemporal=1, per_neighbor=1, push_pack=2),
+          dict(tile_rows=33, pair_rows=1, unroll=1)]
 
 
 @pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f32", 1), ("f64", 1), ("f32", 64)])

@@ -44,7 +44,9 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
                 (False, dict(push_pack=2, unroll=2, nontemporal=1)),
                 (False, dict(push_pack=2, lds_window=1, tile_rows=64, unroll=2)),
                 (True, dict(push_pack=2, lds_window=1, unroll=1)),
-                (False, dict(push_pack=2, lds_window=2, tile_rows=5000))]
+                (False, dict(push_pack=2, lds_window=2, tile_rows=5000)),
+                (False, dict(push_pack=2, lds_window=2, pair_rows=1, tile_rows=50, unroll=4)),
+                (True, dict(push_pack=2, lds_window=2, pair_rows=1, blocks_per_cu=1 << 20))]
     ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
     out = OM.forward_all([D.plan(r, variant) for r in range(R)], xh, rs) if full_stages else None
     for plain_launch, sched in variants:
