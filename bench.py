@@ -5,7 +5,7 @@ Default workload ("batched256"): 256 independent persistent exchange plans,
 halo sizes log-uniform in [1e3, 1e6) rows, 1..4096 neighbors, 16 FP64
 columns per row.  One step = Start + Wait of all plans (pack, unpack) plus
 the backward of the pack (fixed-order transpose sum), each phase one
-persistent kernel replayed from a hipGraph.  The same work as one launch per
+multi-job kernel replayed from a hipGraph.  The same work as one launch per
 plan per phase ("plain") is timed beside it.
 
 Other workloads (``--workload``): random_rows / random_rows_f32 /
@@ -361,7 +361,7 @@ def main():
             log(f"plain:   {plain_ms:.3f} ms/step; phases (ms) {json.dumps({k: round(v, 4) for k, v in pph.items()})}")
     step_bytes = sum(v for ph_id, v in nbytes.items() if ph_id != 3 or 3 in S["phases"])
     value = step_bytes / (ms * 1e-3) / 1e9
-    # dominant kernel: each phase's persistent kernel timed alone (same launch
+    # dominant kernel: each phase's kernel timed alone (same launch
     # table as the graphs, same stream), the longest one of the step
     names = {0: "pack", 1: "redist", 2: "unpack", 3: "backward"}
     with torch.cuda.stream(stream):

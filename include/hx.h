@@ -276,7 +276,7 @@ int hx_backward(hx_req* req, void* stream);
 int hx_req_free(hx_req** req);
 
 /* ---------------------------------------------------------------------------
- * Batches: many persistent requests driven as one (one persistent kernel per
+ * Batches: many persistent requests driven as one (one multi-job kernel per
  * phase, captured in a hipGraph at init and replayed by start/wait).
  *
  * hx_batch_init: members are existing requests (same dtype and ncols); they
@@ -310,8 +310,10 @@ int hx_req_free(hx_req** req);
  *   rows per lane x pack form x LDS windows x rows per lane pairing (8-byte
  *   rows), then launch shape (persistent or one-shot grid, workgroup size) x
  *   streaming hints, then the first dimensions again; each candidate is the
- *   average of three back-to-back launches, best of two trials.  With
- *   HX_TUNE_LOG set, every candidate's time goes to stderr.
+ *   average of three back-to-back launches, best of two trials.  Then the
+ *   replay (see hx_batch_set_replay): graph or direct launches, whichever
+ *   runs 20 start + wait steps faster.  With HX_TUNE_LOG set, every
+ *   candidate's time goes to stderr.
  * ------------------------------------------------------------------------- */
 enum { HX_WORLD_SIM_TRANSFER = 1, HX_WORLD_STAGED_BACKWARD = 2 };
 int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, hx_batch** out);
@@ -338,6 +340,17 @@ int hx_batch_tune(hx_batch* b, void* stream);
 int hx_batch_launch_phase(hx_batch* b, int phase, void* stream);
 /* The schedule in use for a phase (0 pack, 1 redistribution, 2 unpack, 3 backward). */
 int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out);
+/* Replay of start / wait / backward: HX_REPLAY_GRAPH (default) launches the
+ * graph captured at init; HX_REPLAY_DIRECT launches the same prepared launch
+ * tables one by one (no per-call setup either way, same results).  A graph
+ * launch has a fixed cost (about 15 us measured on MI355X, whatever the
+ * graph holds) against about 3 us per directly launched kernel, so steps of
+ * a few short kernels replay faster directly; hx_batch_tune measures a
+ * start + wait both ways and keeps the faster.  Mode other than these two:
+ * HX_ERR_ARG. */
+enum { HX_REPLAY_GRAPH = 0, HX_REPLAY_DIRECT = 1 };
+int hx_batch_set_replay(hx_batch* b, int mode);
+int hx_batch_get_replay(const hx_batch* b, int* mode);
 /* World arenas: which = HX_ARENA_SEND / HX_ARENA_RECV, all ranks concatenated
  * as [stage-1 part of every rank | stage-2 part of every rank].
  * which = HX_ARENA_GRAD_SEND (plain or staged-backward worlds, after

@@ -21,6 +21,7 @@ HX_F32, HX_F64 = 0, 1
 HX_PLAIN, HX_LOCALITY_2STEP, HX_LOCALITY_3STEP = 0, 1, 2
 HX_ARENA_SEND, HX_ARENA_RECV, HX_ARENA_GRAD_SEND = 0, 1, 4
 HX_WORLD_SIM_TRANSFER, HX_WORLD_STAGED_BACKWARD = 1, 2
+HX_REPLAY_GRAPH, HX_REPLAY_DIRECT = 0, 1
 HX_PLAN_MAX_RANKS = 16384
 PHASES = ("pack", "redist", "unpack", "backward")
 
@@ -39,8 +40,8 @@ EXPORTED = (
     "hx_req_bind_grad", "hx_req_enable_ready", "hx_backward", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
     "hx_batch_start", "hx_batch_wait", "hx_batch_start_plain", "hx_batch_wait_plain",
     "hx_batch_bind_grad", "hx_batch_backward", "hx_batch_backward_plain", "hx_batch_tune",
-    "hx_batch_launch_phase", "hx_batch_get_sched", "hx_batch_arena", "hx_batch_arena_offset", "hx_batch_bytes",
-    "hx_batch_free",
+    "hx_batch_launch_phase", "hx_batch_get_sched", "hx_batch_set_replay", "hx_batch_get_replay",
+    "hx_batch_arena", "hx_batch_arena_offset", "hx_batch_bytes", "hx_batch_free",
 )
 
 
@@ -108,6 +109,8 @@ def load() -> C.CDLL:
         "hx_req_enable_ready": (C.c_int, [VP, PP]),
         "hx_batch_launch_phase": (C.c_int, [VP, C.c_int, VP]),
         "hx_batch_get_sched": (C.c_int, [VP, C.c_int, C.POINTER(hx_sched)]),
+        "hx_batch_set_replay": (C.c_int, [VP, C.c_int]),
+        "hx_batch_get_replay": (C.c_int, [VP, C.POINTER(C.c_int)]),
         "hx_batch_arena": (C.c_int, [VP, C.c_int, PP, I64P]),
         "hx_batch_arena_offset": (C.c_int, [VP, C.c_int, C.c_int, I64P]),
         "hx_batch_bytes": (C.c_int, [VP, C.c_int, I64P]),
@@ -372,6 +375,16 @@ def hx_batch_get_sched(b: Batch, phase: int) -> dict:
     s = hx_sched()
     _check(load().hx_batch_get_sched(b.ptr, phase, C.byref(s)))
     return s.as_dict()
+
+
+def hx_batch_set_replay(b: Batch, mode: int) -> None:
+    _check(load().hx_batch_set_replay(b.ptr, mode))
+
+
+def hx_batch_get_replay(b: Batch) -> int:
+    m = C.c_int()
+    _check(load().hx_batch_get_replay(b.ptr, C.byref(m)))
+    return m.value
 
 
 def hx_batch_arena(b: Batch, which: int):

@@ -69,6 +69,7 @@ struct hx_batch {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   bool has_graph[3] = {false, false, false};
+  bool replay_direct = false;  // start / wait / backward launch the tables directly instead of the graphs
   bool active = false;
   bool tuning = false;                      // hx_batch_tune running: candidates skip completion counters
   int64_t bytes[4] = {0, 0, 0, 0};

@@ -119,6 +119,7 @@ int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
   HX_TRY(upload_vec(t->tile_start, ts));
   int64_t want = (int64_t)t->sched.blocks_per_cu * device_cus();
   want = std::min<int64_t>(want, (t->ntiles + 7) / 8 * 8);
+  want = std::min<int64_t>(want, int64_t(1) << 30);  // a launchable grid; larger tables take tile ranges
   want = std::max<int64_t>(8, (want + 7) / 8 * 8);
   t->grid = (int)want;
   return HX_SUCCESS;

@@ -1,12 +1,14 @@
 // Device bodies of the data-movement kernels (included by the move_*.hip
 // translation units, which instantiate and launch them).
 //
-// All kernels are persistent and multi-job: a launch walks a table of jobs
-// cut into tiles of `tile_rows` rows.  Workgroup b runs on XCD b % 8
-// (round-robin dispatch), so logical workgroup ids are regrouped per XCD and
-// each logical workgroup takes a contiguous range of tiles: consecutive tiles
-// -- and the rows they share -- stay in one XCD's L2, and each XCD streams a
-// contiguous stretch of memory.  Rows move as 16/8/4-byte vectors with LPR
+// All kernels are multi-job: a launch walks a table of jobs cut into tiles
+// of `tile_rows` rows.  Workgroup b runs on XCD b % 8 (round-robin
+// dispatch), so logical workgroup ids are regrouped per XCD and each logical
+// workgroup takes a contiguous range of tiles: consecutive tiles -- and the
+// rows they share -- stay in one XCD's L2.  With a grid as large as the tile
+// count (one-shot) each workgroup takes one tile and the hardware hands them
+// out in order; with a smaller grid (persistent) each walks its range, which
+// lets a job's LDS window be staged once.  Rows move as 16/8/4-byte vectors with LPR
 // lanes per row; U rows per lane are loaded before any is stored, to keep
 // enough bytes in flight for HBM.  LDS carries the rest: CSR-driven kernels
 // stage each tile's row pointers and entry indices (the push pack then runs

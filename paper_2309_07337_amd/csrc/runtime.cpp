@@ -750,10 +750,53 @@ extern "C" int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, 
   return HX_SUCCESS;
 }
 
+// Replays start (0), wait (1) or backward (2): the captured graph, or the
+// same launch tables directly.
 static int launch_graph(hx_batch* b, int which, hipStream_t s) {
+  if (b->replay_direct) {
+    if (which == 0) return batch_run_start(b, s);
+    if (which == 1) return batch_run_wait(b, s);
+    return batch_run_backward(b, s);
+  }
   if (!b->has_graph[which]) return HX_SUCCESS;
   HX_HIP(hipGraphLaunch(b->graph[which], s));
   return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_set_replay(hx_batch* b, int mode) {
+  if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (mode != HX_REPLAY_GRAPH && mode != HX_REPLAY_DIRECT) return fail(HX_ERR_ARG, "bad replay mode %d", mode);
+  b->replay_direct = mode == HX_REPLAY_DIRECT;
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_batch_get_replay(const hx_batch* b, int* mode) {
+  if (!b || !mode) return fail(HX_ERR_ARG, "null argument");
+  *mode = b->replay_direct ? HX_REPLAY_DIRECT : HX_REPLAY_GRAPH;
+  return HX_SUCCESS;
+}
+
+// Average time of `reps` start + wait steps in one replay mode (after one
+// warm-up step); the batch keeps that mode.
+static int time_replay(hx_batch* b, hipStream_t s, bool direct, int reps, float* ms) {
+  b->replay_direct = direct;
+  hipEvent_t e0, e1;
+  HX_HIP(hipEventCreate(&e0));
+  HX_HIP(hipEventCreate(&e1));
+  int rc = launch_graph(b, 0, s);
+  if (rc == HX_SUCCESS) rc = launch_graph(b, 1, s);
+  if (rc == HX_SUCCESS && hipEventRecord(e0, s) != hipSuccess) rc = fail(HX_ERR_HIP, "event record");
+  for (int i = 0; i < reps && rc == HX_SUCCESS; ++i) {
+    rc = launch_graph(b, 0, s);
+    if (rc == HX_SUCCESS) rc = launch_graph(b, 1, s);
+  }
+  if (rc == HX_SUCCESS && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+    rc = fail(HX_ERR_HIP, "event timing");
+  if (rc == HX_SUCCESS) *ms /= (float)reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 extern "C" int hx_batch_start(hx_batch* b, void* stream) {
@@ -868,7 +911,7 @@ extern "C" int hx_batch_backward_plain(hx_batch* b, void* stream) {
 
 int hx::batch_run_backward(hx_batch* b, hipStream_t s) { return run_backward(b, s, false); }
 
-// One phase's persistent kernel on its own, launched directly from the same
+// One phase's kernel on its own, launched directly from the same
 // launch table the graphs replay (for per-kernel timing).
 extern "C" int hx_batch_launch_phase(hx_batch* b, int phase, void* stream) {
   if (!b) return fail(HX_ERR_ARG, "null batch");
@@ -1018,9 +1061,22 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->tuning = false;  // the tables kept for Start/Wait signal their counters again
   HX_TRY(rc);
-  return batch_prepare(b);
+  // replay: the captured graphs, or the same tables launched directly where
+  // that measures faster (a graph launch has a fixed cost).  The trial runs
+  // on tables built while tuning, which signal no completion counters.
+  HX_TRY(batch_prepare(b));
+  float ms_graph = 0, ms_direct = 0;
+  int rr = time_replay(b, s, false, 20, &ms_graph);
+  if (rr == HX_SUCCESS) rr = time_replay(b, s, true, 20, &ms_direct);
+  const bool direct = rr == HX_SUCCESS && ms_direct < ms_graph * 0.98f;
+  if (log && rr == HX_SUCCESS)
+    std::fprintf(stderr, "hx tune replay: graph %.4f ms, direct %.4f ms per start + wait -> %s\n", ms_graph,
+                 ms_direct, direct ? "direct" : "graph");
+  b->tuning = false;  // the tables kept for Start/Wait signal their counters again
+  HX_TRY(batch_prepare(b));
+  b->replay_direct = direct;
+  return rr;
 }
 
 extern "C" int hx_batch_free(hx_batch** b) {

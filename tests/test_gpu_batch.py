@@ -105,6 +105,38 @@ def test_batch_graph_equals_plain_equals_oracle(dtype_name, ncols):
         b.free()
 
 
+@pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f64", 1)])
+def test_direct_replay_equals_graph_and_oracle(dtype_name, ncols):
+    """Start / wait / backward launched directly from the prepared tables give
+    the graph replay's results bit for bit, also after a re-prepare (bind)."""
+    need_gpu()
+    import torch
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    say("direct replay", dtype_name, ncols)
+    mem = build_members(12, 20000, ncols, dtype)
+    b = P.hx_batch_init([m["req"] for m in mem])
+    assert P.hx_batch_get_replay(b) == P.HX_REPLAY_GRAPH
+    P.hx_batch_set_replay(b, P.HX_REPLAY_DIRECT)
+    assert P.hx_batch_get_replay(b) == P.HX_REPLAY_DIRECT
+    for rep in range(3):
+        reset(mem)
+        torch.cuda.synchronize()
+        P.hx_batch_start(b)
+        P.hx_batch_wait(b)
+        P.hx_batch_backward(b)
+        check_members(mem, ncols, dtype)
+    P.hx_batch_set_replay(b, P.HX_REPLAY_GRAPH)
+    reset(mem)
+    P.hx_batch_start(b)
+    P.hx_batch_wait(b)
+    P.hx_batch_backward(b)
+    check_members(mem, ncols, dtype)
+    with pytest.raises(P.HXError) as e:
+        P.hx_batch_set_replay(b, 2)
+    assert e.value.code == P.HX_ERR_ARG
+    b.free()
+
+
 def test_tuner_keeps_results_and_caches(tmp_path, monkeypatch):
     need_gpu()
     import torch
@@ -124,6 +156,13 @@ def test_tuner_keeps_results_and_caches(tmp_path, monkeypatch):
     b2 = P.hx_batch_init([m["req"] for m in mem])
     assert [P.hx_batch_get_sched(b2, ph) for ph in range(4)] == scheds
     assert all(P.hx_batch_bytes(b, ph) > 0 for ph in (0, 2, 3))
+    # the tuner also chose a replay; results hold in it
+    assert P.hx_batch_get_replay(b) in (P.HX_REPLAY_GRAPH, P.HX_REPLAY_DIRECT)
+    reset(mem)
+    P.hx_batch_start(b)
+    P.hx_batch_wait(b)
+    P.hx_batch_backward(b)
+    check_members(mem, 16, torch.float64)
 
 
 def test_batch_state_machine():

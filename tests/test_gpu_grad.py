@@ -197,7 +197,8 @@ def staged_exchange(rs, rp, cols, ppn, variant, ncols, dtype, sim=True):
 @pytest.mark.parametrize("case", CASES)
 def test_staged_backward_tiny_bit_exact(case, variant):
     """Backward through the plan's stages == the oracle's staged adjoint, bit
-    for bit, in the graph and in the one-launch-per-rank form."""
+    for bit, in the graph, in the one-launch-per-rank form and launched
+    directly from the batched tables."""
     need_gpu()
     import torch
     n, R, mx, pf, seed, uneven, ppn = case
@@ -218,6 +219,12 @@ def test_staged_backward_tiny_bit_exact(case, variant):
     P.hx_batch_backward_plain(ex.batch)
     torch.cuda.synchronize()
     assert bits_equal(host(ex.g_x), want)
+    ex.g_x.fill_(float("nan"))
+    P.hx_batch_set_replay(ex.batch, P.HX_REPLAY_DIRECT)   # same tables, no graph
+    P.hx_batch_backward(ex.batch)
+    torch.cuda.synchronize()
+    assert bits_equal(host(ex.g_x), want)
+    P.hx_batch_set_replay(ex.batch, P.HX_REPLAY_GRAPH)
     if variant == "plain":   # the closed form, whichever flag
         assert bits_equal(want, OM.exchange_adjoint_reference(halos, gy, n))
 

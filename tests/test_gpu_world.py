@@ -15,10 +15,16 @@ pytestmark = pytest.mark.gpu
 
 
 def run_world(plan, x, H, plain_launch=False, sched=None):
+    """plain_launch: False = graph replay, True = one launch per rank,
+    "direct" = the batched tables launched directly (no graph)."""
     import torch
     halo = torch.full((H, x.shape[1]), float("nan"), dtype=x.dtype, device="cuda")
     b = P.hx_batch_from_plan(plan, x, halo, flags=P.HX_WORLD_SIM_TRANSFER, sched=sched)
-    if plain_launch:
+    if plain_launch == "direct":
+        P.hx_batch_set_replay(b, P.HX_REPLAY_DIRECT)
+        P.hx_batch_start(b)
+        P.hx_batch_wait(b)
+    elif plain_launch:
         P.hx_batch_start_plain(b)
         P.hx_batch_wait_plain(b)
     else:
@@ -46,7 +52,8 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
                 (True, dict(push_pack=2, lds_window=1, unroll=1)),
                 (False, dict(push_pack=2, lds_window=2, tile_rows=5000)),
                 (False, dict(push_pack=2, lds_window=2, pair_rows=1, tile_rows=50, unroll=4)),
-                (True, dict(push_pack=2, lds_window=2, pair_rows=1, blocks_per_cu=1 << 20))]
+                (True, dict(push_pack=2, lds_window=2, pair_rows=1, blocks_per_cu=1 << 20)),
+                ("direct", None), ("direct", dict(push_pack=1, tile_rows=40, blocks_per_cu=1 << 20))]
     ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
     out = OM.forward_all([D.plan(r, variant) for r in range(R)], xh, rs) if full_stages else None
     for plain_launch, sched in variants:
