@@ -371,8 +371,12 @@ def main():
     dom = names[dom_p]
     achieved = nbytes[dom_p] / (kms[dom_p] * 1e-3) / 1e9
     kname = {"pack": "k_pack", "redist": "k_redist", "unpack": "k_unpack", "backward": "k_segsum"}[dom]
-    if dom == "pack" and P.hx_batch_get_sched(b, 0)["push_pack"] == 1:
+    sch = P.hx_batch_get_sched(b, dom_p)
+    row_bytes = S["cfg"].get("ncols", 16) * (8 if S["dtype"] == "f64" else 4)
+    if dom == "pack" and sch["push_pack"] == 1:
         kname = "k_pack_push"
+    elif dom != "backward" and sch["pair_rows"] == 1 and row_bytes == 8:
+        kname += "_pair"   # 8-byte rows two per lane
     log(f"kernels alone (ms): {json.dumps({names[p]: round(t, 4) for p, t in kms.items()})}")
     traffic = read_traffic(kname, args.workload)
     cpu = cpu_baseline(S, args.cpu_seconds) if S["host"] else None
