@@ -11,20 +11,27 @@
 namespace hx {
 namespace {
 
-// bad[j] = 1 when some index of job j lies outside its source window.
+// bad[j] = 1 when more than half of job j's indices lie outside its source
+// window (rows outside a window are read from global memory, so a window
+// that holds few of them only costs its staging).
 __global__ void __launch_bounds__(256) k_check_windows(const GatherJob* __restrict__ jobs, int njobs,
                                                        int32_t* __restrict__ bad) {
+  __shared__ unsigned long long s_out;
   for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
     const GatherJob g = jobs[j];
-    int out = 0;
+    if (threadIdx.x == 0) s_out = 0;
+    __syncthreads();
+    unsigned long long out = 0;
     if (g.win_rows > 0 && g.idx != nullptr) {
       for (int64_t e = threadIdx.x; e < g.nrows; e += blockDim.x) {
         const int64_t v = g.idx[e];
-        out |= (v < g.win_lo || v >= g.win_lo + g.win_rows) ? 1 : 0;
+        out += (v < g.win_lo || v >= g.win_lo + g.win_rows) ? 1 : 0;
       }
     }
-    out = __syncthreads_or(out);
-    if (threadIdx.x == 0) bad[j] = out ? 1 : 0;
+    if (out) atomicAdd(&s_out, out);  // LDS atomic
+    __syncthreads();
+    if (threadIdx.x == 0) bad[j] = 2 * (int64_t)s_out > g.nrows ? 1 : 0;
+    __syncthreads();  // s_out is reset for the next job
   }
 }
 
@@ -47,7 +54,8 @@ __global__ void __launch_bounds__(256) k_tile_terms(const SegSumJob* __restrict_
   }
 }
 
-// Clears the windows of jobs whose indices leave them (device-side check).
+// Clears the windows of jobs that hold less than half of their indices
+// (device-side count).
 int drop_bad_windows(std::vector<GatherJob>* w) {
   std::vector<int> at;
   for (size_t i = 0; i < w->size(); ++i)

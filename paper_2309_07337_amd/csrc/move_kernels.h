@@ -94,12 +94,13 @@ __device__ __forceinline__ int find_job(const int64_t* __restrict__ ts, int njob
 // (NV = 0: runtime nv, then U must be 1), LPR lanes per row.
 // ---------------------------------------------------------------------------
 // Source windows (use_win != 0, fixed shapes only): a job with win_rows > 0
-// reads only source rows [win_lo, win_lo + win_rows) (the table builder
-// checks every index on the device and drops windows that do not hold), and
-// the table's dynamic LDS holds that many rows.  The workgroup copies the
-// window into LDS with coalesced loads when it reaches a new such job and
-// then gathers from LDS: one wide read of the window instead of one L2
-// request per (usually short, scattered) row.
+// reads mostly source rows [win_lo, win_lo + win_rows) (the table builder
+// counts them on the device and drops windows that hold less than half of
+// a job's indices), and the table's dynamic LDS holds that many rows.  The
+// workgroup copies the window into LDS with coalesced loads when it reaches
+// a new such job and then gathers rows inside it from LDS, the others from
+// global memory: one wide read of the window instead of one L2 request per
+// (usually short, scattered) row.
 template <int VB, int NV, int LPR, int U, bool NT>
 __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
                                             int njobs, int64_t ntiles, int tile_rows, int nv_rt, int use_win) {
@@ -181,9 +182,7 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
     if constexpr (NV > 0) {
       // Lanes past the tile's end re-read its last row, so every index and
       // row load is valid and the U loads of a lane go out together (no
-      // branch between them); only the stores are predicated.  Every index
-      // of a windowed job lies in its window (checked when the table was
-      // built).
+      // branch between them); only the stores are predicated.
       const bool in_lds = win_rows > 0;
       for (int64_t base = r0 + rsub; base < r1; base += (int64_t)rows_per_pass * U) {
         V v[U][NVPL];
@@ -194,13 +193,19 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
           srow[u] = idx ? (int64_t)ldv<int32_t, NT>(idx + r) : r;
         }
         if (in_lds) {
+          // rows inside the window from LDS, the others from global memory
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int64_t wr = srow[u] - win_lo;
+            const bool inw = (uint64_t)wr < (uint64_t)win_rows;
+            const V* sp = reinterpret_cast<const V*>(src + srow[u] * rb);
 #pragma unroll
             for (int k = 0; k < NVPL; ++k) {
               const int vi = lane_v + k * LPR;
-              if (NV % LPR == 0 || vi < NV) v[u][k] = s_win[wr * NV + vi];
+              if (NV % LPR == 0 || vi < NV) {
+                if (inw) v[u][k] = s_win[wr * NV + vi];
+                else v[u][k] = sp[vi];
+              }
             }
           }
         } else {
