@@ -81,9 +81,9 @@ typedef struct hx_batch hx_batch;
  * (tiles never straddle neighbors); 0 tiles each member's rows flat. */
 typedef struct {
   int tile_rows;      /* rows per tile (work unit of one workgroup iteration) */
-  int block_threads;  /* 256 or 512; 1024 is taken by the segmented sums
-                         (backward) only, which then read no LDS term
-                         windows; the gathers run it as 512 */
+  int block_threads;  /* 256, 512 or 1024 (the push pack runs 1024 as 512;
+                         segmented sums with 1024 lanes read no LDS term
+                         windows) */
   int blocks_per_cu;  /* grid = blocks_per_cu * #CUs workgroups, each walking
                          a contiguous range of tiles, but never more than
                          the tile count (rounded up to 8): a value of at

@@ -100,8 +100,8 @@ int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
     return fail(HX_ERR_ARG, "invalid schedule (tile_rows %d, block_threads %d, blocks_per_cu %d)",
                 t->sched.tile_rows, t->sched.block_threads, t->sched.blocks_per_cu);
   if (t->sched.block_threads != 256 && t->sched.block_threads != 512 &&
-      !(kind == KIND_SEGSUM && t->sched.block_threads == 1024))
-    return fail(HX_ERR_ARG, "block_threads must be 256 or 512 (1024: segmented sums only)");
+      !(kind != KIND_SCATTER && t->sched.block_threads == 1024))
+    return fail(HX_ERR_ARG, "block_threads must be 256, 512 or 1024");
   // keep only jobs with rows; tile prefix
   std::vector<J> kept;
   std::vector<int64_t> ts(1, 0);
@@ -236,7 +236,9 @@ int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_by
 int build_scatter_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
                         LaunchTable* t, int tag) {
   t->tag = tag;
-  HX_TRY(build_table(jobs, KIND_SCATTER, dtype, row_bytes, s, t, align_of(jobs, row_bytes)));
+  Sched sc = s;
+  sc.block_threads = std::min(sc.block_threads, 512);  // the push pack runs at most 512 lanes
+  HX_TRY(build_table(jobs, KIND_SCATTER, dtype, row_bytes, sc, t, align_of(jobs, row_bytes)));
   return fill_tile_terms(t);
 }
 

@@ -9,13 +9,13 @@ namespace {
 
 #define HX_GATHER_KERNEL(NAME)                                                                 \
   template <int VB, int NV, int LPR, int U, bool NT>                                           \
-  __global__ void __launch_bounds__(512)                                                       \
+  __global__ void __launch_bounds__(1024)                                                      \
       NAME(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs,      \
            int64_t ntiles, int tile_rows, int nv_rt, int use_win) {                            \
     gather_body<VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt, use_win);       \
   }                                                                                            \
   template <int U, bool NT>                                                                    \
-  __global__ void __launch_bounds__(512)                                                       \
+  __global__ void __launch_bounds__(1024)                                                      \
       NAME##_pair(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs, \
                   int64_t ntiles, int tile_rows) {                                             \
     gather_pair_body<U, NT>(jobs, ts, njobs, ntiles, tile_rows);                               \

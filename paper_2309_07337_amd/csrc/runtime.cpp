@@ -138,7 +138,6 @@ Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
   if (!p) return s;
   if (p->tile_rows > 0) s.tile_rows = p->tile_rows;
   if (p->block_threads > 0) s.block_threads = p->block_threads;
-  if (s.block_threads == 1024 && kind != KIND_SEGSUM) s.block_threads = 512;
   if (p->blocks_per_cu > 0) s.blocks_per_cu = p->blocks_per_cu;
   s.nontemporal = p->nontemporal ? 1 : 0;
   s.per_neighbor = p->per_neighbor ? 1 : 0;
@@ -1038,14 +1037,19 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
       const Sched s1 = best;
       for (int bpc : {2, 4, 8, kOneShotBpc})
         for (int bt : {256, 512, 1024})
-          for (int nt : {0, 1}) {
-            if (bt == 1024 && ph != PH_BWD) continue;  // segmented sums only
-            Sched c = s1;
-            c.blocks_per_cu = bpc;
-            c.block_threads = bt;
-            c.nontemporal = nt;
-            consider(c);
-          }
+          for (int nt : {0, 1})
+            for (int flip : {0, 1}) {
+              // (gathers: LDS windows again with each launch shape, where the
+              // occupancy they allow depends on the workgroup size)
+              if (bt == 1024 && ph == PH_PACK && s1.push_pack) continue;  // push pack: at most 512 lanes
+              if (flip && (ph == PH_BWD || (ph == PH_PACK && s1.push_pack) || s1.pair_rows)) continue;
+              Sched c = s1;
+              c.lds_window = flip ? !s1.lds_window : s1.lds_window;
+              c.blocks_per_cu = bpc;
+              c.block_threads = bt;
+              c.nontemporal = nt;
+              consider(c);
+            }
     }
     tile_stage();
     // stage 4: one job per message (member batches, pull forms)

@@ -71,7 +71,10 @@ SCHEDS = [None,
           # 8-byte rows two per lane (even tiles; odd job ends are half pairs)
           dict(tile_rows=64, blocks_per_cu=1 << 20, pair_rows=1, unroll=4),
           dict(tile_rows=1000, pair_rows=1, unroll=2, nontemporal=1, per_neighbor=1, push_pack=2),
-          dict(tile_rows=33, pair_rows=1, unroll=1)]
+          dict(tile_rows=33, pair_rows=1, unroll=1),
+          # 1024-lane gathers (the push pack runs 512), with windows and pairs
+          dict(tile_rows=4096, block_threads=1024, blocks_per_cu=2, lds_window=1, push_pack=2, unroll=2),
+          dict(tile_rows=128, block_threads=1024, blocks_per_cu=1 << 20, pair_rows=1, push_pack=1)]
 
 
 @pytest.mark.parametrize("dtype_name,ncols", [("f64", 16), ("f32", 1), ("f64", 1), ("f32", 64)])

@@ -53,7 +53,9 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
                 (False, dict(push_pack=2, lds_window=2, tile_rows=5000)),
                 (False, dict(push_pack=2, lds_window=2, pair_rows=1, tile_rows=50, unroll=4)),
                 (True, dict(push_pack=2, lds_window=2, pair_rows=1, blocks_per_cu=1 << 20)),
-                ("direct", None), ("direct", dict(push_pack=1, tile_rows=40, blocks_per_cu=1 << 20))]
+                ("direct", None), ("direct", dict(push_pack=1, tile_rows=40, blocks_per_cu=1 << 20)),
+                (False, dict(push_pack=2, lds_window=1, block_threads=1024, blocks_per_cu=2, tile_rows=300)),
+                (False, dict(push_pack=1, pair_rows=1, block_threads=1024, blocks_per_cu=1 << 20))]
     ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
     out = OM.forward_all([D.plan(r, variant) for r in range(R)], xh, rs) if full_stages else None
     for plain_launch, sched in variants:
