@@ -98,15 +98,17 @@ typedef struct {
                          to all its slots); 2 = pull form (gather per slot);
                          0 = default (push for rows of 64 bytes or more,
                          else pull) */
-  int lds_window;     /* gathers: 1 = a job whose indices stay inside a known
-                         window of source rows (the pack: the rank's own
-                         rows; the redistribution: its stage-1 receive
+  int lds_window;     /* gathers: 1 = a job whose indices mostly stay inside
+                         a known window of source rows (the pack: the rank's
+                         own rows; the redistribution: its stage-1 receive
                          arena; a world's unpack: its stage-2 receive arena)
                          copies that window into LDS (when it fits in 80 KiB
-                         and every index is inside it, checked on the device
-                         when the launch table is built) and gathers from
-                         LDS; 2 = gather from global memory; 0 = default (1
-                         for rows of 16 bytes or less, else 2) */
+                         and holds at least half of the job's indices,
+                         counted on the device when the launch table is
+                         built) and gathers rows inside it from LDS, the
+                         others from global memory; 2 = gather from global
+                         memory; 0 = default (1 for rows of 16 bytes or
+                         less, else 2) */
   int pair_rows;      /* gathers of 8-byte rows: 1 = two rows per lane (one
                          8-byte load of the index pair, one 16-byte store;
                          taken where every destination is 16-byte aligned,
