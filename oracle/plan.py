@@ -17,7 +17,7 @@ Source passages (MPI Advance, Bienz, Schafer, Skjellum, 2023):
   (global) indices of every value sent and received and uses them so that a
   value crosses between a pair of nodes only once.
 
-Readings of what the paper leaves open (each also listed in the design doc):
+Readings of what the paper leaves open:
 
 * R1  contiguous ownership: rank p owns rows/columns [row_starts[p], row_starts[p+1]).
 * R2  block placement: node(p) = p // ppn, lrank(p) = p % ppn; the last node

@@ -73,7 +73,7 @@ def load() -> C.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2309_07337_amd.build)")
     lib = C.CDLL(LIB_PATH)
     sig = {
         "hx_error_string": (C.c_char_p, [C.c_int]),
