@@ -335,7 +335,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: one rank's share (or a batch of "
+        print(json.dumps({"error": "hx runs on one GPU only: one rank's share (or a batch of "
                                    "ranks) per GPU; no collectives between GPUs. Use --gpus 1."}))
         sys.exit(2)
     import torch
