@@ -145,6 +145,55 @@ def test_finite_differences():
         assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (r, c, counts[r], fd, g)
 
 
+def test_finite_differences_random_rows_64_columns():
+    """The differentiation workload at full size: random-matrix plan (4096
+    ranks), 64 FP32 features.  Central differences of L = sum(w * Y) at
+    h = 1e-3, for inputs drawn from every fan-out class, evaluated as the
+    float64 sum of w * (Y(x + h) - Y(x - h)) over the halo entries that
+    changed (every other entry of that difference is exactly zero, so no
+    rounding of the 2.6 G-term loss enters), divided by the realised step,
+    against the backward with w as the halo gradient:
+    |g_fd - g| <= 1e-6 * max(1, |g|)."""
+    need_gpu()
+    import torch
+    rs, rp, cols = cached_random_rows()
+    halos = OP.all_halos(rp, cols, rs)
+    n = int(rs[-1])
+    C = 64
+    say("finite differences random_rows, 64 columns")
+    ex, _ = exchange_for(rs, rp, cols, 128, "plain", C)
+    H = ex.halo.shape[0]
+    x0 = dev(uniform_pm1_f32(9, n * C).reshape(n, C))
+    step = 1 << 22
+    for lo in range(0, H, step):
+        hi = min(H, lo + step)
+        ex.g_halo[lo:hi] = dev(uniform_pm1_f32(10, (hi - lo) * C, start=lo * C).reshape(hi - lo, C))
+    ex.x.copy_(x0)
+    ex.forward()
+    gx = ex.backward()
+    torch.cuda.synchronize()
+    counts = np.bincount(np.concatenate(halos), minlength=n)
+    rng = np.random.default_rng(2)
+    picks = []
+    for f in np.unique(counts):
+        rows = np.nonzero(counts == f)[0]
+        picks += [(int(r), int(rng.integers(C))) for r in rng.choice(rows, size=min(2, rows.size), replace=False)]
+    h = np.float32(1e-3)
+    for (r, c) in picks[:48]:
+        v = float(x0[r, c])
+        vp, vm = np.float32(v) + h, np.float32(v) - h
+        ex.x[r, c] = float(vp)
+        yp = ex.forward()[:, c].clone()
+        ex.x[r, c] = float(vm)
+        ym = ex.forward()[:, c]
+        ch = (yp != ym).nonzero().flatten()
+        assert ch.numel() == counts[r], (r, c)   # every halo entry that reads row r, and no other
+        fd = float((ex.g_halo[ch, c].double() * (yp[ch].double() - ym[ch].double())).sum()) / (float(vp) - float(vm))
+        ex.x[r, c] = v
+        g = float(gx[r, c])
+        assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (r, c, counts[r], fd, g)
+
+
 @pytest.mark.parametrize("sim", [True, False])
 @pytest.mark.parametrize("variant", ["plain", "locality"])
 def test_world_backward_plain_launch_equals_graph(variant, sim):
