@@ -311,8 +311,9 @@ int hx_req_free(hx_req** req);
  *   (file named by HX_TUNE_CACHE, if set).  Search per phase: tile size x
  *   rows per lane x pack form x LDS windows x rows per lane pairing (8-byte
  *   rows), then launch shape (persistent or one-shot grid, workgroup size) x
- *   streaming hints, then the first dimensions again; each candidate is the
- *   average of three back-to-back launches, best of two trials.  Then the
+ *   streaming hints, then the first dimensions again, then rows per lane x
+ *   launch shape together; each candidate is the average of three
+ *   back-to-back launches, best of two trials.  Then the
  *   replay (see hx_batch_set_replay): graph or direct launches, whichever
  *   runs 20 start + wait steps faster.  With HX_TUNE_LOG set, every
  *   candidate's time goes to stderr.

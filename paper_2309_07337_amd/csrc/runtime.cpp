@@ -1010,7 +1010,8 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     // stage 1: work per tile, rows in flight, pull vs push (pack), LDS
     // source windows and two rows per lane (gathers); stage 2: launch shape
     // (persistent or one-shot grid, workgroup size) and streaming hints;
-    // stage 3: stage 1 again around the new launch shape
+    // stage 3: stage 1 again around the new launch shape; stage 4: rows in
+    // flight x launch shape
     auto tile_stage = [&]() {
       const Sched s0 = best;
       for (int tf : {1, 2, 4, 8, 16, 32})
@@ -1052,7 +1053,22 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
             }
     }
     tile_stage();
-    // stage 4: one job per message (member batches, pull forms)
+    // stage 4: rows in flight and launch shape together around the chosen
+    // tile (the stage-by-stage search can stop at a near tie between them)
+    {
+      const Sched s3 = best;
+      for (int u : {1, 2, 4})
+        for (int bpc : {2, 4, 8, kOneShotBpc})
+          for (int bt : {256, 512, 1024}) {
+            if (bt == 1024 && ph == PH_PACK && s3.push_pack) continue;  // push pack: at most 512 lanes
+            Sched c = s3;
+            c.unroll = u;
+            c.blocks_per_cu = bpc;
+            c.block_threads = bt;
+            consider(c);
+          }
+    }
+    // stage 5: one job per message (member batches, pull forms)
     if (!b->world && !(ph == PH_PACK && best.push_pack) && ph != PH_BWD) {
       Sched c = best;
       c.per_neighbor = 1;
