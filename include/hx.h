@@ -313,7 +313,8 @@ int hx_req_free(hx_req** req);
  *   rows), then launch shape (persistent or one-shot grid, workgroup size) x
  *   streaming hints, then the first dimensions again, then rows per lane x
  *   launch shape together; each candidate is the average of three
- *   back-to-back launches, best of two trials.  Then the
+ *   back-to-back launches (short kernels: about a millisecond of launches,
+ *   at most 50), best of two trials.  Then the
  *   replay (see hx_batch_set_replay): graph or direct launches, whichever
  *   runs 20 start + wait steps faster.  With HX_TUNE_LOG set, every
  *   candidate's time goes to stderr.
