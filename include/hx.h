@@ -127,6 +127,35 @@ const char* hx_last_error_message(void);
 const char* hx_version(void);
 
 /* ---------------------------------------------------------------------------
+ * Device memory allocator -- Sec. 2.4 (the library works on device memory
+ * of the caller's memory space).
+ *
+ * Every device allocation the library makes (plan arrays, send / receive
+ * arenas, launch tables, temporaries of the plan build) goes through
+ * alloc_fn(bytes, stream, ctx), where stream is the hipStream_t the memory
+ * is first used on (NULL when the call has none: the legacy default
+ * stream), and is returned through free_fn(ptr, ctx).  alloc_fn returns
+ * device memory of the current device, aligned to at least 16 bytes, or
+ * NULL on failure; the library then fails the call with HX_ERR_NOMEM and
+ * frees whatever that call had already allocated (no leak).  A pointer
+ * that is not 16-byte aligned is returned at once through free_fn and the
+ * call fails with HX_ERR_ARG.  Before free_fn runs the library waits for
+ * the device to be idle (as hipFree does), so the allocator may hand the
+ * block out again at once.
+ * hx_set_allocator(NULL, NULL, NULL) restores hipMalloc / hipFree.  The
+ * setting is process-wide and applies to allocations made after the call;
+ * each block is freed through the free_fn that was installed when it was
+ * allocated, so alloc_fn, free_fn and ctx must stay valid until every
+ * handle allocated under them is freed.  Exactly one of the two functions
+ * NULL: HX_ERR_ARG.  The Python binding installs torch's caching allocator
+ * (torch.cuda.caching_allocator_alloc / _delete), so torch sees and reuses
+ * the library's memory.
+ * ------------------------------------------------------------------------- */
+typedef void* (*hx_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*hx_free_fn)(void* ptr, void* ctx);
+int hx_set_allocator(hx_alloc_fn alloc_fn, hx_free_fn free_fn, void* ctx);
+
+/* ---------------------------------------------------------------------------
  * Neighbor topology -- Listing 4 (MPIX_Dist_graph_create_adjacent).
  *
  * rank, nranks: this rank and the size of the (simulated) communicator.

@@ -33,7 +33,7 @@ FIELDS = ("halo", "s1_procs", "s1_counts", "s1_displs", "s1_idx",
 FIELD_ID = {k: i for i, k in enumerate(FIELDS)}
 
 EXPORTED = (
-    "hx_error_string", "hx_last_hip_error", "hx_last_error_message", "hx_version",
+    "hx_error_string", "hx_last_hip_error", "hx_last_error_message", "hx_version", "hx_set_allocator",
     "hx_topo_create", "hx_topo_free", "hx_neighbor_alltoallv_init",
     "hx_plan_from_csr", "hx_plan_from_halos", "hx_plan_free", "hx_plan_field_size",
     "hx_plan_field_copy", "hx_req_from_plan", "hx_start", "hx_wait", "hx_req_arena",
@@ -61,6 +61,8 @@ class hx_sched(C.Structure):
 
 
 _lib = None
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 VP = C.c_void_p
 PP = C.POINTER(C.c_void_p)
 I32P = C.POINTER(C.c_int32)
@@ -80,6 +82,7 @@ def load() -> C.CDLL:
         "hx_last_hip_error": (C.c_int, []),
         "hx_last_error_message": (C.c_char_p, []),
         "hx_version": (C.c_char_p, []),
+        "hx_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, VP]),
         "hx_topo_create": (C.c_int, [C.c_int, C.c_int, C.c_int, I32P, I32P, C.c_int, I32P, I32P, C.c_int, PP]),
         "hx_topo_free": (C.c_int, [PP]),
         "hx_neighbor_alltoallv_init": (C.c_int, [VP, C.c_int64, I32P, I32P, I32P, VP, I32P, I32P, C.c_int,
@@ -121,7 +124,64 @@ def load() -> C.CDLL:
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    use_torch_allocator()
     return lib
+
+
+# ---------------------------------------------------------------------------
+# Device memory: the library allocates through torch's caching allocator, so
+# torch sees (torch.cuda.memory_allocated) and reuses the arenas and plan
+# arrays.  The callbacks run at init / free time only, never in Start / Wait.
+# ---------------------------------------------------------------------------
+_shutting_down = False
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        s = int(stream) if stream else torch.cuda.current_stream().cuda_stream
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), s)
+    except Exception:      # out of memory (or no device): the library reports HX_ERR_NOMEM
+        return None
+
+
+def _torch_free(ptr, ctx):
+    if _shutting_down or not ptr:
+        return             # the interpreter is exiting: the process releases the memory
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+_TORCH_FREE = FREE_FN(_torch_free)
+_allocator_keep = []        # callbacks installed by hx_set_allocator stay alive here
+
+
+def _at_exit():
+    global _shutting_down
+    _shutting_down = True
+
+
+import atexit  # noqa: E402
+atexit.register(_at_exit)
+
+
+def hx_set_allocator(alloc_fn=None, free_fn=None, ctx=None) -> None:
+    """Installs device allocation callbacks (ctypes ALLOC_FN / FREE_FN
+    objects, or plain Python callables wrapped here); None, None restores
+    hipMalloc / hipFree.  Allocations made afterwards go through them."""
+    if alloc_fn is not None and not isinstance(alloc_fn, ALLOC_FN):
+        alloc_fn = ALLOC_FN(alloc_fn)
+    if free_fn is not None and not isinstance(free_fn, FREE_FN):
+        free_fn = FREE_FN(free_fn)
+    _check(load().hx_set_allocator(alloc_fn if alloc_fn is not None else ALLOC_FN(0),
+                                   free_fn if free_fn is not None else FREE_FN(0), ctx))
+    _allocator_keep.extend([f for f in (alloc_fn, free_fn) if f is not None])
+
+
+def use_torch_allocator() -> None:
+    """Routes the library's device allocations through torch's caching allocator."""
+    _check(_lib.hx_set_allocator(_TORCH_ALLOC, _TORCH_FREE, None))
 
 
 def _check(rc: int) -> None:

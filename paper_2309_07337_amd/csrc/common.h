@@ -31,23 +31,36 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line);
   } while (0)
 
 // ---------------------------------------------------------------------------
-// Device memory owned by library objects.
+// Device memory owned by library objects.  Every allocation goes through the
+// allocator installed with hx_set_allocator (hipMalloc / hipFree when none
+// is); a block remembers the free function of the allocator that made it,
+// so installing another allocator later never mismatches a free.
 // ---------------------------------------------------------------------------
 struct DevMem {
   void* p = nullptr;
   size_t bytes = 0;
+  hx_free_fn free_fn = nullptr;  // nullptr: hipFree
+  void* free_ctx = nullptr;
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem(DevMem&& o) noexcept { take(o); }
   DevMem& operator=(DevMem&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) { release(); take(o); }
     return *this;
   }
   ~DevMem() { release(); }
   void release();
-  int alloc(size_t nbytes);  // frees previous contents; zero bytes -> nullptr
+  // frees previous contents; zero bytes -> nullptr.  stream: the stream the
+  // memory will first be used on (passed to an installed allocator).
+  int alloc(size_t nbytes, hipStream_t stream = nullptr);
   template <class T> T* as() const { return static_cast<T*>(p); }
+
+ private:
+  void take(DevMem& o) {
+    p = o.p; bytes = o.bytes; free_fn = o.free_fn; free_ctx = o.free_ctx;
+    o.p = nullptr; o.bytes = 0; o.free_fn = nullptr; o.free_ctx = nullptr;
+  }
 };
 
 int upload(DevMem& dst, const void* host, size_t bytes);

@@ -30,6 +30,7 @@ struct hx_req {
   int64_t bytes[4] = {0, 0, 0, 0};
   const char* g_send = nullptr;
   char* g_x = nullptr;
+  uint64_t grad_gen = 0;  // changes at every hx_req_bind_grad (unique across requests)
   bool active = false;
   bool tables_built = false;
   hx::LaunchTable lt[4];
@@ -73,7 +74,7 @@ struct hx_batch {
   bool active = false;
   bool tuning = false;                      // hx_batch_tune running: candidates skip completion counters
   int64_t bytes[4] = {0, 0, 0, 0};
-  int64_t bwd_rows_captured = 0;
+  std::vector<uint64_t> bwd_gens_captured;  // members' grad_gen when the backward tables were built
   // world (all ranks of a plan over flat arrays)
   int R = 0;
   int64_t n = 0;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -47,15 +48,56 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
   return e == hipErrorOutOfMemory ? HX_ERR_NOMEM : HX_ERR_HIP;
 }
 
+// Installed allocator (none: hipMalloc / hipFree).
+namespace {
+std::mutex g_alloc_mu;
+hx_alloc_fn g_alloc_fn = nullptr;
+hx_free_fn g_free_fn = nullptr;
+void* g_alloc_ctx = nullptr;
+}  // namespace
+
 void DevMem::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (free_fn) {
+      // the caller's allocator may hand the block out again at once: wait
+      // until no kernel still uses it, as hipFree does
+      (void)hipDeviceSynchronize();
+      free_fn(p, free_ctx);
+    } else {
+      (void)hipFree(p);
+    }
+  }
   p = nullptr;
   bytes = 0;
+  free_fn = nullptr;
+  free_ctx = nullptr;
 }
 
-int DevMem::alloc(size_t nbytes) {
+int DevMem::alloc(size_t nbytes, hipStream_t stream) {
   release();
   if (nbytes == 0) return HX_SUCCESS;
+  hx_alloc_fn af;
+  hx_free_fn ff;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    af = g_alloc_fn;
+    ff = g_free_fn;
+    ctx = g_alloc_ctx;
+  }
+  if (af) {
+    void* q = af(nbytes, (void*)stream, ctx);
+    if (!q) return fail(HX_ERR_NOMEM, "the installed allocator failed to provide %zu bytes", nbytes);
+    if (((uintptr_t)q & 15) != 0) {
+      ff(q, ctx);
+      return fail(HX_ERR_ARG, "the installed allocator returned a pointer that is not 16-byte aligned");
+    }
+    p = q;
+    bytes = nbytes;
+    free_fn = ff;
+    free_ctx = ctx;
+    return HX_SUCCESS;
+  }
   hipError_t e = hipMalloc(&p, nbytes);
   if (e != hipSuccess) {
     p = nullptr;
@@ -467,6 +509,8 @@ extern "C" int hx_req_bind_grad(hx_req* r, const void* g_send, void* g_x) {
   if ((r->E1 > 0 && !g_send) || (r->n_local > 0 && !g_x)) return fail(HX_ERR_ARG, "null gradient buffer");
   r->g_send = static_cast<const char*>(g_send);
   r->g_x = static_cast<char*>(g_x);
+  static std::atomic<uint64_t> bind_counter{0};
+  r->grad_gen = ++bind_counter;  // batches holding this member rebuild their backward
   r->lt[PH_BWD] = LaunchTable();
   std::vector<GatherJob> g;
   std::vector<SegSumJob> s;
@@ -622,12 +666,18 @@ static int build_fwd_sum_table(const hx_batch* b, const Sched& sc, LaunchTable* 
   return build_segsum_table(fjs, b->dtype, (int)b->row_bytes, sc, t, TAG_FWD_SUM);
 }
 
+// Gradient bindings of a member batch's requests (the backward tables and
+// graph hold their g_send / g_x pointers).
+static std::vector<uint64_t> member_grad_gens(const hx_batch* b) {
+  std::vector<uint64_t> v;
+  v.reserve(b->members.size());
+  for (const hx_req* r : b->members) v.push_back(r->grad_gen);
+  return v;
+}
+
 int hx::batch_prepare(hx_batch* b) {
   batch_destroy_graphs(b);
-  if (!b->world) {
-    b->bwd_rows_captured = 0;
-    for (hx_req* r : b->members) b->bwd_rows_captured += (r->g_x ? r->n_local : 0);
-  }
+  if (!b->world) b->bwd_gens_captured = member_grad_gens(b);
   for (int ph = 0; ph < 4; ++ph) HX_TRY(batch_build_table(b, ph, b->sched[ph], &b->lt[ph]));
   HX_TRY(build_fwd_sum_table(b, b->sched[PH_BWD], &b->lt_fwd_sum));
   if (!b->cap_stream) HX_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
@@ -887,24 +937,26 @@ static int run_backward(hx_batch* b, hipStream_t s, bool plain_form) {
   return HX_SUCCESS;
 }
 
+// Member gradients bound (or rebound to other buffers) since the backward
+// tables were built: rebuild the tables (batched and plain) and recapture
+// the graphs.
+static int refresh_member_grads(hx_batch* b) {
+  if (b->world || member_grad_gens(b) == b->bwd_gens_captured) return HX_SUCCESS;
+  b->plain_built[PH_BWD] = false;
+  return batch_prepare(b);
+}
+
 extern "C" int hx_batch_backward(hx_batch* b, void* stream) {
   if (!b) return fail(HX_ERR_ARG, "null batch");
   if (b->world && !b->g_out) return fail(HX_ERR_STATE, "no gradient buffers bound");
-  if (!b->world) {
-    // member gradients may have been bound after the batch was created
-    int64_t rows = 0;
-    for (hx_req* r : b->members) rows += (r->g_x ? r->n_local : 0);
-    if (rows != b->bwd_rows_captured) {
-      b->bwd_rows_captured = rows;
-      b->plain_built[PH_BWD] = false;
-      HX_TRY(batch_prepare(b));
-    }
-  }
+  HX_TRY(refresh_member_grads(b));
   return launch_graph(b, 2, (hipStream_t)stream);
 }
 
 extern "C" int hx_batch_backward_plain(hx_batch* b, void* stream) {
   if (!b) return fail(HX_ERR_ARG, "null batch");
+  if (b->world && !b->g_out) return fail(HX_ERR_STATE, "no gradient buffers bound");
+  HX_TRY(refresh_member_grads(b));
   if (!b->plain_built[PH_BWD]) HX_TRY(batch_build_plain(b, PH_BWD));
   return run_backward(b, (hipStream_t)stream, true);
 }
@@ -919,11 +971,8 @@ extern "C" int hx_batch_launch_phase(hx_batch* b, int phase, void* stream) {
   if (b->active) return fail(HX_ERR_STATE, "batch active: call hx_batch_wait first");
   if (phase == PH_BWD) {
     if (b->world && !b->g_out) return fail(HX_ERR_STATE, "no gradient buffers bound");
-    if (!b->world) {
-      int64_t rows = 0;
-      for (hx_req* r : b->members) rows += (r->g_x ? r->n_local : 0);
-      if (rows != b->bwd_rows_captured) return fail(HX_ERR_STATE, "gradients bound after the last backward: call hx_batch_backward once first");
-    }
+    if (!b->world && member_grad_gens(b) != b->bwd_gens_captured)
+      return fail(HX_ERR_STATE, "gradients bound after the last backward: call hx_batch_backward once first");
   }
   if (phase == PH_BWD && b->world && b->staged_bwd)  // the staged backward's forwarder sums first
     HX_TRY(launch_table(b->lt_fwd_sum, (hipStream_t)stream));
@@ -1124,6 +1173,16 @@ extern "C" const char* hx_error_string(int code) {
     case HX_ERR_HIP: return "HIP runtime error";
     default: return "unknown error";
   }
+}
+
+extern "C" int hx_set_allocator(hx_alloc_fn alloc_fn, hx_free_fn free_fn, void* ctx) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return fail(HX_ERR_ARG, "hx_set_allocator: give both functions or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc_fn = alloc_fn;
+  g_free_fn = free_fn;
+  g_alloc_ctx = alloc_fn ? ctx : nullptr;
+  return HX_SUCCESS;
 }
 
 extern "C" int hx_last_hip_error(void) { return g_hip; }

@@ -117,3 +117,27 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_allocator_failure_is_nomem_without_a_gpu():
+    """The first allocation of an init call fails in the installed allocator:
+    HX_ERR_NOMEM, and nothing is handed to the free callback."""
+    import ctypes as C
+    from paper_2309_07337_amd import _lib as L
+    lib = P.load()
+    calls, frees = [], []
+    try:
+        P.hx_set_allocator(lambda n, s, c: calls.append(n), lambda p, c: frees.append(p))
+        topo = P.hx_topo_create(0, 2, [1], [1])
+        sc = np.array([2], np.int32)
+        si = np.array([0, 3], np.int32)
+        out = C.c_void_p()
+        rc = lib.hx_neighbor_alltoallv_init(0x1000, 4, sc.ctypes.data_as(L.I32P), None, si.ctypes.data_as(L.I32P),
+                                            0x2000, sc.ctypes.data_as(L.I32P), None, P.HX_F64, 1, topo.ptr,
+                                            C.byref(out))
+        assert rc == P.HX_ERR_NOMEM and not out.value
+        assert len(calls) == 1 and not frees
+        # exactly one of the two callbacks: an argument error
+        assert lib.hx_set_allocator(L._TORCH_ALLOC, L.FREE_FN(0), None) == P.HX_ERR_ARG
+    finally:
+        L.use_torch_allocator()

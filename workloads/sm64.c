@@ -2,8 +2,10 @@
  *
  * Input generation only: output i of the stream seeded with s is
  * mix(s + (i + 1) * GAMMA).  Produces exactly the values of the numpy
- * implementation in gen.py (checked by the test suite); it exists because the
- * batched workload needs ~10^9 values and numpy's 64-bit multiply is slow.
+ * implementation in gen.py (tests/test_inputs_cpu.py compares the two, and
+ * the stream with the published generator's first outputs); it exists
+ * because the batched workload needs ~10^9 values and numpy's 64-bit
+ * multiply is slow.
  */
 #include <stdint.h>
 
