@@ -304,6 +304,39 @@ int hx_req_bind_grad(hx_req* req, const void* g_send, void* g_x);
  * while the request is active. */
 int hx_req_enable_ready(hx_req* req, unsigned long long** dev_counters);
 int hx_backward(hx_req* req, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Backward that allocates nothing.  For callers that cannot allocate device
+ * memory during the call: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.
+ *
+ * Computes what hx_req_bind_grad(req, g_send, g_x) followed by
+ * hx_backward(req, stream) computes, bit for bit: for every local row i,
+ * g_x[i] = sum over the stage-1 send slots k packed from row i, ascending k,
+ * of g_send[k] (first term first, +0.0 for rows never packed).  g_send
+ * device [E1, ncols] (may be NULL when E1 = 0), g_x device [n_local, ncols],
+ * both in the request's dtype; they are used by this call only and the
+ * request's bound gradients are left as they are.
+ * The segmented sum's launch table (job descriptor, tile prefix and each
+ * tile's entry range) is written by a kernel on stream into a fixed
+ * library-owned device area of HX_NOALLOC_SCRATCH_BYTES per GPU, held from
+ * the first call on that GPU until the process ends, instead of device
+ * memory allocated for the request: the call makes no allocation (neither
+ * hipMalloc nor the installed allocator) and no memset, only two kernel
+ * launches on stream.
+ * Limit: the sum's tiles, ceil(n_local / tile_rows) with tile_rows between
+ * 64 and 512 chosen from the row size (512 for rows of 128 bytes or less),
+ * must fit the area: at most (HX_NOALLOC_SCRATCH_BYTES - 512) / 8 = 131008
+ * tiles; beyond that the call fails with HX_ERR_UNSUPPORTED and launches
+ * nothing.
+ * Every call on a GPU uses that GPU's one area: calls issued in order on one
+ * stream are safe, calls that overlap on one GPU (other streams, or threads
+ * without ordering) race and give wrong results.
+ * Errors: HX_ERR_ARG (null request, null g_send with E1 > 0, null g_x with
+ * n_local > 0), HX_ERR_UNSUPPORTED, HX_ERR_HIP.
+ * ------------------------------------------------------------------------- */
+#define HX_NOALLOC_SCRATCH_BYTES (1u << 20)
+int hx_backward_noalloc(hx_req* req, const void* g_send, void* g_x, void* stream);
 int hx_req_free(hx_req** req);
 
 /* ---------------------------------------------------------------------------

@@ -23,6 +23,7 @@ HX_ARENA_SEND, HX_ARENA_RECV, HX_ARENA_GRAD_SEND = 0, 1, 4
 HX_WORLD_SIM_TRANSFER, HX_WORLD_STAGED_BACKWARD = 1, 2
 HX_REPLAY_GRAPH, HX_REPLAY_DIRECT = 0, 1
 HX_PLAN_MAX_RANKS = 16384
+HX_NOALLOC_SCRATCH_BYTES = 1 << 20
 PHASES = ("pack", "redist", "unpack", "backward")
 
 FIELDS = ("halo", "s1_procs", "s1_counts", "s1_displs", "s1_idx",
@@ -37,7 +38,7 @@ EXPORTED = (
     "hx_topo_create", "hx_topo_free", "hx_neighbor_alltoallv_init",
     "hx_plan_from_csr", "hx_plan_from_halos", "hx_plan_free", "hx_plan_field_size",
     "hx_plan_field_copy", "hx_req_from_plan", "hx_start", "hx_wait", "hx_req_arena",
-    "hx_req_bind_grad", "hx_req_enable_ready", "hx_backward", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
+    "hx_req_bind_grad", "hx_req_enable_ready", "hx_backward", "hx_backward_noalloc", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
     "hx_batch_start", "hx_batch_wait", "hx_batch_start_plain", "hx_batch_wait_plain",
     "hx_batch_bind_grad", "hx_batch_backward", "hx_batch_backward_plain", "hx_batch_tune",
     "hx_batch_launch_phase", "hx_batch_get_sched", "hx_batch_set_replay", "hx_batch_get_replay",
@@ -98,6 +99,7 @@ def load() -> C.CDLL:
         "hx_req_arena": (C.c_int, [VP, C.c_int, PP, I64P]),
         "hx_req_bind_grad": (C.c_int, [VP, VP, VP]),
         "hx_backward": (C.c_int, [VP, VP]),
+        "hx_backward_noalloc": (C.c_int, [VP, VP, VP, VP]),
         "hx_req_free": (C.c_int, [PP]),
         "hx_batch_init": (C.c_int, [PP, C.c_int, C.POINTER(hx_sched), PP]),
         "hx_batch_from_plan": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, C.c_int, C.POINTER(hx_sched), PP]),
@@ -371,6 +373,12 @@ def hx_req_enable_ready(req: Req) -> int:
 
 def hx_backward(req: Req, stream=None) -> None:
     _check(load().hx_backward(req.ptr, _stream(stream)))
+
+
+def hx_backward_noalloc(req: Req, g_send, g_x, stream=None) -> None:
+    """The request's backward into g_x from g_send, allocating nothing (the
+    launch table goes to the library's fixed per-device area)."""
+    _check(load().hx_backward_noalloc(req.ptr, _dptr(g_send), _dptr(g_x), _stream(stream)))
 
 
 def _sched_ptr(sched):

@@ -41,6 +41,7 @@ struct DevMem {
   size_t bytes = 0;
   hx_free_fn free_fn = nullptr;  // nullptr: hipFree
   void* free_ctx = nullptr;
+  bool owned = true;             // false: a view of memory owned elsewhere (never freed here)
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
@@ -54,12 +55,19 @@ struct DevMem {
   // frees previous contents; zero bytes -> nullptr.  stream: the stream the
   // memory will first be used on (passed to an installed allocator).
   int alloc(size_t nbytes, hipStream_t stream = nullptr);
+  // views nbytes at q (memory this object does not own and never frees)
+  void borrow(void* q, size_t nbytes) {
+    release();
+    p = q;
+    bytes = nbytes;
+    owned = false;
+  }
   template <class T> T* as() const { return static_cast<T*>(p); }
 
  private:
   void take(DevMem& o) {
-    p = o.p; bytes = o.bytes; free_fn = o.free_fn; free_ctx = o.free_ctx;
-    o.p = nullptr; o.bytes = 0; o.free_fn = nullptr; o.free_ctx = nullptr;
+    p = o.p; bytes = o.bytes; free_fn = o.free_fn; free_ctx = o.free_ctx; owned = o.owned;
+    o.p = nullptr; o.bytes = 0; o.free_fn = nullptr; o.free_ctx = nullptr; o.owned = true;
   }
 };
 
@@ -179,6 +187,17 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
                        const Sched& s, LaunchTable* t, int tag = TAG_TRANSFER);
 int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes,
                        const Sched& s, LaunchTable* t, int tag = TAG_OWNER_SUM);
+// The same table for one job, written by a kernel on stream into caller-
+// provided device memory `area` of area_bytes (job descriptor, tile prefix,
+// tile entry ranges; nothing is allocated), then launched on stream.  The
+// area must stay untouched until the launch has run.  HX_ERR_UNSUPPORTED when
+// the tile entry ranges do not fit (limit: segsum_area_max_tiles).
+int launch_segsum_in_area(const SegSumJob& job, int dtype, int row_bytes, const Sched& s, void* area,
+                          size_t area_bytes, hipStream_t stream, int tag = TAG_OWNER_SUM);
+constexpr size_t kAreaHeadBytes = 512;  // job descriptor and tile prefix ahead of the entry ranges
+inline int64_t segsum_area_max_tiles(size_t area_bytes) {
+  return area_bytes <= kAreaHeadBytes ? 0 : (int64_t)((area_bytes - kAreaHeadBytes) / sizeof(int2));
+}
 int build_scatter_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes,
                         const Sched& s, LaunchTable* t, int tag = TAG_PACK);
 int launch_table(const LaunchTable& t, hipStream_t stream);

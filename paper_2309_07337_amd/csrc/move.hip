@@ -54,6 +54,25 @@ __global__ void __launch_bounds__(256) k_tile_terms(const SegSumJob* __restrict_
   }
 }
 
+// The launch table of a single segmented-sum job written in place: the job
+// descriptor, the tile prefix {0, ntiles} and every tile's entry range (as
+// k_tile_terms), all from the kernel's arguments and the job's row pointers.
+__global__ void __launch_bounds__(256) k_area_table(SegSumJob job, int64_t ntiles, int tile_rows,
+                                                    SegSumJob* __restrict__ jobs, int64_t* __restrict__ ts,
+                                                    int2* __restrict__ te) {
+  const int64_t first = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (first == 0) {
+    jobs[0] = job;
+    ts[0] = 0;
+    ts[1] = ntiles;
+  }
+  for (int64_t t = first; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r0 = t * (int64_t)tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, job.nrows);
+    te[t] = make_int2(job.ptr[r0], job.ptr[r1]);
+  }
+}
+
 // Clears the windows of jobs that hold less than half of their indices
 // (device-side count).
 int drop_bad_windows(std::vector<GatherJob>* w) {
@@ -89,9 +108,11 @@ int pick_vec(int row_bytes, uintptr_t align_or) {
   return 0;
 }
 
+// Launch shape of a table (schedule checks, the jobs with rows and their tile
+// prefix, vector width, grid); allocates nothing.
 template <class J>
-int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, const Sched& s0, LaunchTable* t,
-                uintptr_t align_or) {
+int shape_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, const Sched& s0, LaunchTable* t,
+                uintptr_t align_or, std::vector<J>* kept_out, std::vector<int64_t>* ts_out) {
   t->kind = kind;
   t->dtype = dtype;
   t->row_bytes = row_bytes;
@@ -103,8 +124,10 @@ int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
       !(kind != KIND_SCATTER && t->sched.block_threads == 1024))
     return fail(HX_ERR_ARG, "block_threads must be 256, 512 or 1024");
   // keep only jobs with rows; tile prefix
-  std::vector<J> kept;
-  std::vector<int64_t> ts(1, 0);
+  std::vector<J>& kept = *kept_out;
+  std::vector<int64_t>& ts = *ts_out;
+  kept.clear();
+  ts.assign(1, 0);
   for (const J& j : jobs) {
     if (j.nrows <= 0) continue;
     kept.push_back(j);
@@ -123,13 +146,23 @@ int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
   if (t->vec_bytes == 0) return fail(HX_ERR_ARG, "rows of %d bytes / buffers not 4-byte aligned", row_bytes);
   if (kind == KIND_SEGSUM && (size_t)t->vec_bytes < dtype_bytes(dtype))
     return fail(HX_ERR_ARG, "FP64 buffers must be 8-byte aligned");
-  HX_TRY(upload_vec(t->jobs, kept));
-  HX_TRY(upload_vec(t->tile_start, ts));
   int64_t want = (int64_t)t->sched.blocks_per_cu * device_cus();
   want = std::min<int64_t>(want, (t->ntiles + 7) / 8 * 8);
   want = std::min<int64_t>(want, int64_t(1) << 30);  // a launchable grid; larger tables take tile ranges
   want = std::max<int64_t>(8, (want + 7) / 8 * 8);
   t->grid = (int)want;
+  return HX_SUCCESS;
+}
+
+template <class J>
+int build_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, const Sched& s0, LaunchTable* t,
+                uintptr_t align_or) {
+  std::vector<J> kept;
+  std::vector<int64_t> ts;
+  HX_TRY(shape_table(jobs, kind, dtype, row_bytes, s0, t, align_or, &kept, &ts));
+  if (t->ntiles == 0) return HX_SUCCESS;
+  HX_TRY(upload_vec(t->jobs, kept));
+  HX_TRY(upload_vec(t->tile_start, ts));
   return HX_SUCCESS;
 }
 
@@ -195,8 +228,10 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
   return HX_SUCCESS;
 }
 
-int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
-                       LaunchTable* t, int tag) {
+// Shape of a segmented-sum table: term windows, launch shape, term buffer
+// (no device memory).
+int shape_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
+                       LaunchTable* t, int tag, std::vector<SegSumJob>* kept, std::vector<int64_t>* ts) {
   t->tag = tag;
   // term windows: kept where the schedule asks for them, they fit, and they
   // lie inside one of the two inputs
@@ -224,13 +259,47 @@ int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_by
     if (j.win_rows > 0 && j.nrows > 0)
       a |= (uintptr_t)(j.win_lo < j.split ? j.in + j.win_lo * (int64_t)row_bytes
                                            : j.in2 + (j.win_lo - j.split) * (int64_t)row_bytes);
-  HX_TRY(build_table(w, KIND_SEGSUM, dtype, row_bytes, s, t, a));
+  HX_TRY(shape_table(w, KIND_SEGSUM, dtype, row_bytes, s, t, a, kept, ts));
   t->win_bytes = t->ntiles > 0 ? (int)win_bytes : 0;
   // term buffer: about two terms per tile row, at least 4 KiB and at most
   // kSegValueBytes, whole rows (small tiles leave LDS for more workgroups)
   int64_t vb = std::min<int64_t>(kSegValueBytes, std::max<int64_t>(4096, 2 * (int64_t)s.tile_rows * row_bytes));
   t->val_bytes = t->ntiles > 0 && row_bytes > 0 ? (int)(vb / row_bytes * row_bytes) : 0;
+  return HX_SUCCESS;
+}
+
+int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
+                       LaunchTable* t, int tag) {
+  std::vector<SegSumJob> kept;
+  std::vector<int64_t> ts;
+  HX_TRY(shape_segsum_table(jobs, dtype, row_bytes, s, t, tag, &kept, &ts));
+  if (t->ntiles == 0) return HX_SUCCESS;
+  HX_TRY(upload_vec(t->jobs, kept));
+  HX_TRY(upload_vec(t->tile_start, ts));
   return fill_tile_terms(t);
+}
+
+int launch_segsum_in_area(const SegSumJob& job, int dtype, int row_bytes, const Sched& s, void* area,
+                          size_t area_bytes, hipStream_t stream, int tag) {
+  LaunchTable t;
+  std::vector<SegSumJob> kept;
+  std::vector<int64_t> ts;
+  HX_TRY(shape_segsum_table(std::vector<SegSumJob>(1, job), dtype, row_bytes, s, &t, tag, &kept, &ts));
+  if (t.ntiles == 0) return HX_SUCCESS;
+  if (t.ntiles > segsum_area_max_tiles(area_bytes))
+    return fail(HX_ERR_UNSUPPORTED, "%lld tiles of %d rows exceed the %lld a %zu-byte area holds",
+                (long long)t.ntiles, t.sched.tile_rows, (long long)segsum_area_max_tiles(area_bytes), area_bytes);
+  if (area == nullptr || ((uintptr_t)area % 256) != 0) return fail(HX_ERR_ARG, "area must be 256-byte aligned");
+  static_assert(sizeof(SegSumJob) + 2 * sizeof(int64_t) <= kAreaHeadBytes, "area head");
+  char* base = static_cast<char*>(area);
+  t.jobs.borrow(base, sizeof(SegSumJob));
+  t.tile_start.borrow(base + 256, 2 * sizeof(int64_t));
+  t.tile_terms.borrow(base + kAreaHeadBytes, (size_t)t.ntiles * sizeof(int2));
+  const int grid = (int)std::min<int64_t>((t.ntiles + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_area_table, dim3(grid), dim3(256), 0, stream, kept[0], t.ntiles, t.sched.tile_rows,
+                     t.jobs.as<SegSumJob>(), t.tile_start.as<int64_t>(), t.tile_terms.as<int2>());
+  HX_HIP(hipGetLastError());
+  return launch_table(t, stream);
 }
 
 int build_scatter_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,

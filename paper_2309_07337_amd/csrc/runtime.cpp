@@ -57,7 +57,7 @@ void* g_alloc_ctx = nullptr;
 }  // namespace
 
 void DevMem::release() {
-  if (p) {
+  if (p && owned) {
     if (free_fn) {
       // the caller's allocator may hand the block out again at once: wait
       // until no kernel still uses it, as hipFree does
@@ -71,6 +71,7 @@ void DevMem::release() {
   bytes = 0;
   free_fn = nullptr;
   free_ctx = nullptr;
+  owned = true;
 }
 
 int DevMem::alloc(size_t nbytes, hipStream_t stream) {

@@ -3,6 +3,7 @@ by default), allocation failures injected through the allocator callback,
 gradient rebinding of batch members, and the autograd Function's output
 buffers."""
 import ctypes as C
+import gc
 
 import numpy as np
 import pytest
@@ -40,6 +41,7 @@ def test_torch_allocator_accounts_for_arenas():
     x = dev(uniform_pm1(11, h * ncols).reshape(h, ncols))
     halo = torch.zeros(h, ncols, dtype=torch.float64, device="cuda")
     topo = P.hx_topo_create(0, 4096, lists["procs"], lists["procs"])
+    gc.collect()  # handles of earlier tests still held by reference cycles free their memory now
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated()
     req = P.hx_neighbor_alltoallv_init(x, lists["counts"], lists["displs"], lists["send_idx"], halo,
@@ -138,6 +140,7 @@ def test_hipmalloc_restored():
         x = dev(uniform_pm1(11, h * 3).reshape(h, 3))
         halo = torch.zeros(h, 3, dtype=torch.float64, device="cuda")
         topo = P.hx_topo_create(0, 4096, lists["procs"], lists["procs"])
+        gc.collect()
         torch.cuda.synchronize()
         before = torch.cuda.memory_allocated()
         req = P.hx_neighbor_alltoallv_init(x, lists["counts"], lists["displs"], lists["send_idx"], halo,
