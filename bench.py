@@ -287,12 +287,41 @@ def time_kernels(torch, P, batch, reps, phases):
     return out
 
 
-def cpu_baseline(setup, budget_s):
-    """The oracle as it stands (numpy, one thread) on the same plans and the
-    same byte accounting: pack, identity unpack and fixed-order backward per
-    plan (the transpose of the pack map is init work, built untimed), passes
-    over the host-resident plans repeated until about budget_s of CPU time."""
+def host_cpu():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def _plan_bytes(U, E, h, rb):
+    """Algorithmic bytes of one plan step: pack, identity unpack, backward."""
+    return (E + U) * rb + 4 * E + 2 * h * rb + (E + h) * rb + 4 * (E + h + 1)
+
+
+def cpu_baseline(setup, budget_s, c_runs=20, c_sample_bytes=6e9):
+    """The oracle as it stands on the host's cores, same plans and byte
+    accounting as the GPU step (pack, identity unpack, fixed-order backward;
+    the transpose of the pack map is init work, built untimed):
+
+    * all cores: the plain OpenMP loops of oracle/cpu_move.c over the first
+      plans (about c_sample_bytes of algorithmic bytes per step), median of
+      c_runs timed steps after two untimed ones;
+    * one core: the numpy oracle, passes over the plans until about
+      budget_s of CPU time (reported beside it)."""
     import numpy as np
+    from oracle import cpu as OC
     from oracle import move as OM
     from oracle import plan as OP
     plans = []
@@ -300,24 +329,53 @@ def cpu_baseline(setup, budget_s):
         h, C = hk["x"].shape
         E = hk["idx"].size
         ptr, perm = OP.transpose_csr(hk["idx"], h)
-        plans.append((hk, ptr, perm, np.arange(h, dtype=np.int32), np.unique(hk["idx"]).size, E, h, C * 8))
+        plans.append((hk, ptr, perm, np.arange(h, dtype=np.int32), np.unique(hk["idx"]).size, E, h,
+                      C * hk["x"].dtype.itemsize))
+    model, ncpu, usable = host_cpu()
+    # all cores: C loops, preallocated outputs
+    sample, sbytes = [], 0
+    for pl in plans:
+        if sbytes >= c_sample_bytes:
+            break
+        hk, ptr, perm, ident, U, E, h, rb = pl
+        outs = (np.empty((E,) + hk["x"].shape[1:], hk["x"].dtype), np.empty_like(hk["recv"]),
+                np.empty_like(hk["x"]))
+        sample.append((pl, outs))
+        sbytes += _plan_bytes(U, E, h, rb)
+    times = []
+    for it in range(c_runs + 2):
+        t0 = time.perf_counter()
+        for (hk, ptr, perm, ident, U, E, h, rb), (send, halo, gx) in sample:
+            OC.gather(hk["x"], hk["idx"], out=send)
+            OC.gather(hk["recv"], None, out=halo)
+            OC.transpose_sum(send, ptr, perm, out=gx)   # any [E, C] gradient of this shape
+        if it >= 2:
+            times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    # one core: the numpy oracle
     done_bytes, t, passes, nplans = 0, 0.0, 0, 0
     while t < budget_s and plans:
         for hk, ptr, perm, ident, U, E, h, rb in plans:
             t0 = time.perf_counter()
             OM.pack(hk["x"], hk["idx"])
             OM.gather_rows(hk["recv"], ident)
-            OM.pack_transpose(hk["x"][:E], ptr, perm)   # any [E, C] gradient of this shape
+            OM.pack_transpose(hk["x"][:E], ptr, perm)
             t += time.perf_counter() - t0
-            done_bytes += (E + U) * rb + 4 * E + 2 * h * rb + (E + h) * rb + 4 * (E + h + 1)
+            done_bytes += _plan_bytes(U, E, h, rb)
             nplans += 1
             if t >= budget_s:
                 break
         passes += 1
-    return {"value": round(done_bytes / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nplans} plan steps over the first {len(plans)} of 256 plans ({passes} pass(es), "
-                      f"{done_bytes / 1e9:.2f} GB algorithmic in {t:.1f} s): numpy pack (np.take), identity "
-                      "unpack, fixed-order transpose sum"}
+    return {"value": round(sbytes / med / 1e9, 3), "unit": "GB/s", "cores": OC.threads(), "kind": "oracle",
+            "sample": f"first {len(sample)} of 256 plans ({sbytes / 1e9:.2f} GB algorithmic per step): pack, "
+                      f"identity unpack and fixed-order transpose sum as plain OpenMP C loops, median of "
+                      f"{c_runs} steps ({med * 1e3:.1f} ms)",
+            "cpu_model": model, "nproc": ncpu, "cpus_usable": usable,
+            "numpy_1core": {"value": round(done_bytes / t / 1e9, 3) if t > 0 else None, "unit": "GB/s", "cores": 1,
+                            "kind": "oracle",
+                            "sample": f"{nplans} plan steps over the first {len(plans)} of 256 plans ({passes} "
+                                      f"pass(es), {done_bytes / 1e9:.2f} GB algorithmic in {t:.1f} s): numpy "
+                                      "pack (np.take), identity unpack, fixed-order transpose sum"}}
 
 
 def main():
@@ -332,7 +390,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-plans", type=int, default=256)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "hx runs on one GPU only: one rank's share (or a batch of "

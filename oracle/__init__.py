@@ -12,6 +12,10 @@ Contents (each function cites the passage it follows):
 * ``plan``  : halo discovery, owner segmentation, send-list transpose, the
               locality-aware 2-step plan (node dedup + on-node redistribution)
               and the transpose CSR used by the backward.
+* ``cpu``   : ctypes loader of ``cpu_move.c``, the same pack / gather /
+              fixed-order transpose sum as plain OpenMP loops (the all-cores
+              CPU baseline of the benchmark), pinned by
+              ``tests/test_cpu_oracle.py``.
 * ``move``  : pack, simulated transfer, redistribution pack, unpack, the
               fixed-order transpose sum (backward), the backward taken
               through the plan's stages, and the plain definitions they must
