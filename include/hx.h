@@ -92,7 +92,9 @@ typedef struct {
                          in tile order */
   int nontemporal;    /* 1: streaming (non-temporal) loads/stores of index and output */
   int per_neighbor;   /* see above */
-  int unroll;         /* rows per lane in flight: 1, 2 or 4 (0 = default) */
+  int unroll;         /* rows per lane in flight: 1, 2 or 4 (0 = default);
+                         with pair_rows = 1, 16-byte row groups per lane:
+                         1, 2, 4 or 8 */
   int push_pack;      /* pack phase only: 1 = push form (walk the transpose of
                          the pack map, read each source row once and write it
                          to all its slots); 2 = pull form (gather per slot);
@@ -109,12 +111,16 @@ typedef struct {
                          others from global memory; 2 = gather from global
                          memory; 0 = default (1 for rows of 16 bytes or
                          less, else 2) */
-  int pair_rows;      /* gathers of 8-byte rows: 1 = two rows per lane (one
-                         8-byte load of the index pair, one 16-byte store;
-                         taken where every destination is 16-byte aligned,
-                         every index list 8-byte aligned, the tile size even
-                         and no LDS window is used); 2 = one row per lane;
-                         0 = default (2) */
+  int pair_rows;      /* gathers of 4- or 8-byte rows: 1 = 16 bytes of rows
+                         per lane (a group of four or two consecutive rows
+                         takes one vector load of its indices and one
+                         16-byte store; with LDS windows the window is
+                         staged while the tile's indices are in flight),
+                         taken where every job's index list is congruent
+                         with its destination (one first row aligns both);
+                         2 = one row per lane; 0 = default (1 for rows of
+                         4 or 8 bytes, with 16384-row tiles, 512 lanes, one
+                         workgroup per tile and 4 groups per lane) */
 } hx_sched;
 
 /* ---------------------------------------------------------------------------
@@ -406,6 +412,13 @@ int hx_batch_tune(hx_batch* b, void* stream);
 int hx_batch_launch_phase(hx_batch* b, int phase, void* stream);
 /* The schedule in use for a phase (0 pack, 1 redistribution, 2 unpack, 3 backward). */
 int hx_batch_get_sched(const hx_batch* b, int phase, hx_sched* out);
+/* Sets the schedule of one phase (zero fields: library defaults, as for
+ * hx_batch_init) and rebuilds the launch tables and graphs, so that a
+ * schedule recorded with hx_batch_get_sched (or tuned elsewhere) can be
+ * applied without tuning; the tuning cache is not written.  HX_ERR_ARG
+ * (null, bad phase, an invalid schedule: the batch then keeps its previous
+ * one), HX_ERR_STATE while a Start is pending. */
+int hx_batch_set_sched(hx_batch* b, int phase, const hx_sched* sched);
 /* Replay of start / wait / backward: HX_REPLAY_GRAPH (default) launches the
  * graph captured at init; HX_REPLAY_DIRECT launches the same prepared launch
  * tables one by one (no per-call setup either way, same results).  A graph

@@ -41,7 +41,7 @@ EXPORTED = (
     "hx_req_bind_grad", "hx_req_enable_ready", "hx_backward", "hx_backward_noalloc", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
     "hx_batch_start", "hx_batch_wait", "hx_batch_start_plain", "hx_batch_wait_plain",
     "hx_batch_bind_grad", "hx_batch_backward", "hx_batch_backward_plain", "hx_batch_tune",
-    "hx_batch_launch_phase", "hx_batch_get_sched", "hx_batch_set_replay", "hx_batch_get_replay",
+    "hx_batch_launch_phase", "hx_batch_get_sched", "hx_batch_set_sched", "hx_batch_set_replay", "hx_batch_get_replay",
     "hx_batch_arena", "hx_batch_arena_offset", "hx_batch_bytes", "hx_batch_free",
 )
 
@@ -114,6 +114,7 @@ def load() -> C.CDLL:
         "hx_req_enable_ready": (C.c_int, [VP, PP]),
         "hx_batch_launch_phase": (C.c_int, [VP, C.c_int, VP]),
         "hx_batch_get_sched": (C.c_int, [VP, C.c_int, C.POINTER(hx_sched)]),
+        "hx_batch_set_sched": (C.c_int, [VP, C.c_int, C.POINTER(hx_sched)]),
         "hx_batch_set_replay": (C.c_int, [VP, C.c_int]),
         "hx_batch_get_replay": (C.c_int, [VP, C.POINTER(C.c_int)]),
         "hx_batch_arena": (C.c_int, [VP, C.c_int, PP, I64P]),
@@ -443,6 +444,11 @@ def hx_batch_get_sched(b: Batch, phase: int) -> dict:
     s = hx_sched()
     _check(load().hx_batch_get_sched(b.ptr, phase, C.byref(s)))
     return s.as_dict()
+
+
+def hx_batch_set_sched(b: Batch, phase: int, sched) -> None:
+    """Applies a schedule (dict of hx_sched fields, or hx_sched) to one phase."""
+    _check(load().hx_batch_set_sched(b.ptr, phase, _sched_ptr(sched)))
 
 
 def hx_batch_set_replay(b: Batch, mode: int) -> None:

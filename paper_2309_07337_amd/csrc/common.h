@@ -131,10 +131,10 @@ struct Sched {
   int blocks_per_cu = 0;
   int nontemporal = 0;
   int per_neighbor = 0;
-  int unroll = 0;     // rows per lane in flight: 2, 4, 8 (0 = 4)
+  int unroll = 0;     // rows per lane in flight: 1, 2, 4 (16-byte row groups per lane: also 8)
   int push_pack = 0;  // pack in push form (read each source row once)
   int lds_window = 0; // gathers stage each job's source window in LDS
-  int pair_rows = 0;  // gathers of 8-byte rows: two rows per lane
+  int pair_rows = 0;  // gathers of 4- or 8-byte rows: 16 bytes of rows per lane (2 or 4 rows)
 };
 Sched default_sched(int kind, int row_bytes);
 
@@ -172,7 +172,7 @@ struct LaunchTable {
   int vec_bytes = 0;  // 16, 8 or 4: divides row_bytes and all base pointers
   int win_bytes = 0;  // dynamic LDS of a gather table whose jobs use windows
   int val_bytes = 0;  // segmented sums: dynamic LDS term buffer (whole rows)
-  int pair = 0;       // gathers of 8-byte rows: two rows per lane (alignment and tile size allow it)
+  int vec16 = 0;      // gathers of 4- or 8-byte rows in 16-byte groups per lane (alignment allows it)
   Sched sched;
   int njobs = 0;
   int64_t ntiles = 0;

@@ -199,12 +199,29 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
     if (j.nrows <= 0) continue;
     a |= (uintptr_t)j.src | (uintptr_t)j.dst;
   }
-  // source windows: kept where the schedule asks for them and they fit
+  // short rows in 16-byte groups per lane: rows of 4 or 8 bytes whose
+  // buffers are aligned to the row size, and every index list congruent
+  // with its destination (the first row whose destination is 16-byte
+  // aligned also aligns the V-wide index loads, V = 16 / row_bytes)
+  bool vec = s.pair_rows && (row_bytes == 8 || row_bytes == 4) && (a % (uintptr_t)row_bytes) == 0;
+  if (vec) {
+    const uintptr_t V = 16 / (uintptr_t)row_bytes;
+    for (const auto& j : jobs) {
+      if (j.nrows <= 0 || j.idx == nullptr) continue;
+      if (((uintptr_t)j.idx % 4) != 0 || ((uintptr_t)j.idx / 4) % V != ((uintptr_t)j.dst / row_bytes) % V)
+        vec = false;
+    }
+  }
+  // source windows: kept where the schedule asks for them and they fit (the
+  // 16-byte group form stages from the window's 16-byte aligned start)
   std::vector<GatherJob> w(jobs);
   const int64_t win_cap = std::min<int64_t>(kWinBytes, device_lds_per_block());
-  for (auto& j : w) {
+  auto win_span = [&](const GatherJob& j) -> int64_t {
     const int64_t bytes = j.win_rows * (int64_t)row_bytes;
-    if (!s.lds_window || j.idx == nullptr || j.win_rows <= 0 || bytes > win_cap || j.win_lo < 0) {
+    return vec ? bytes + (int64_t)(((uintptr_t)j.src + (uintptr_t)(j.win_lo * row_bytes)) & 15) : bytes;
+  };
+  for (auto& j : w) {
+    if (!s.lds_window || j.idx == nullptr || j.win_rows <= 0 || win_span(j) > win_cap || j.win_lo < 0) {
       j.win_lo = 0;
       j.win_rows = 0;
     }
@@ -213,18 +230,13 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
   int64_t win_bytes = 0;
   for (const auto& j : w) {
     if (j.win_rows <= 0) continue;
-    a |= (uintptr_t)(j.src + j.win_lo * (int64_t)row_bytes);
-    win_bytes = std::max(win_bytes, j.win_rows * (int64_t)row_bytes);
+    if (!vec) a |= (uintptr_t)(j.src + j.win_lo * (int64_t)row_bytes);
+    win_bytes = std::max(win_bytes, win_span(j));
   }
   HX_TRY(build_table(w, KIND_GATHER, dtype, row_bytes, s, t, a));
   // (the runtime-row-size kernel form ignores windows and reads global memory)
-  t->win_bytes = t->ntiles > 0 ? (int)win_bytes : 0;
-  // 8-byte rows two per lane: 16-byte aligned destinations, 8-byte aligned
-  // index pairs (even tile starts), no windows
-  bool pair = s.pair_rows && row_bytes == 8 && t->vec_bytes == 8 && t->win_bytes == 0 && t->sched.tile_rows % 2 == 0;
-  for (const auto& j : w)
-    if (j.nrows > 0 && (((uintptr_t)j.dst % 16) != 0 || ((uintptr_t)j.idx % 8) != 0)) pair = false;
-  t->pair = t->ntiles > 0 && pair ? 1 : 0;
+  t->win_bytes = t->ntiles > 0 ? (int)((win_bytes + 15) / 16 * 16) : 0;
+  t->vec16 = t->ntiles > 0 && vec ? 1 : 0;
   return HX_SUCCESS;
 }
 

@@ -1,5 +1,6 @@
 // Pull-form row gathers: pack (Start), redistribution pack and unpack (Wait),
-// and the simulated transfer.  One kernel symbol per phase (same body), so
+// and the simulated transfer; short rows also in 16-byte groups per lane
+// (the *_vec symbols).  One kernel symbol per phase (same body), so
 // profiles attribute time to each phase separately.
 #include "move_launch.h"
 
@@ -14,23 +15,23 @@ namespace {
            int64_t ntiles, int tile_rows, int nv_rt, int use_win) {                            \
     gather_body<VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt, use_win);       \
   }                                                                                            \
-  template <int U, bool NT>                                                                    \
+  template <int RB, int U, bool NT>                                                            \
   __global__ void __launch_bounds__(1024)                                                      \
-      NAME##_pair(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs, \
-                  int64_t ntiles, int tile_rows) {                                             \
-    gather_pair_body<U, NT>(jobs, ts, njobs, ntiles, tile_rows);                               \
+      NAME##_vec(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs, \
+                 int64_t ntiles, int tile_rows) {                                              \
+    gather_vec_body<RB, U, NT>(jobs, ts, njobs, ntiles, tile_rows);                            \
   }                                                                                            \
+  struct NAME##_vgo {                                                                          \
+    template <int RB, int U, bool NT>                                                          \
+    static void go(const LaunchTable& t, hipStream_t s) {                                      \
+      hipLaunchKernelGGL((NAME##_vec<RB, U, NT>), dim3(t.grid), dim3(t.sched.block_threads),   \
+                         (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                     \
+                         t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows);    \
+    }                                                                                          \
+  };                                                                                           \
   struct NAME##_go {                                                                           \
     template <int VB, int NV, int LPR, int U, bool NT>                                         \
     static void go(const LaunchTable& t, hipStream_t s, int nv) {                              \
-      if constexpr (VB == 8 && NV == 1 && LPR == 1) {                                          \
-        if (t.pair) {                                                                          \
-          hipLaunchKernelGGL((NAME##_pair<U, NT>), dim3(t.grid), dim3(t.sched.block_threads), 0, \
-                             s, t.jobs.as<GatherJob>(), t.tile_start.as<int64_t>(), t.njobs,   \
-                             t.ntiles, t.sched.tile_rows);                                     \
-          return;                                                                              \
-        }                                                                                      \
-      }                                                                                        \
       hipLaunchKernelGGL((NAME<VB, NV, LPR, U, NT>), dim3(t.grid), dim3(t.sched.block_threads), \
                          (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                     \
                          t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows, nv, \
@@ -67,11 +68,40 @@ void transfer_shape(const LaunchTable& t, hipStream_t s) {
   return transfer_fixed::go<VB, 0, 1, 1, false>(t, s, nv);
 }
 
+// Short rows, 16 bytes per lane (the table builder set t.vec16): rows of 4
+// or 8 bytes, U groups per lane in {1, 2, 4, 8}.
+template <class F, int RB>
+void vec_by_unroll(const LaunchTable& t, hipStream_t s) {
+  const bool nt = t.sched.nontemporal != 0;
+  // (eight groups of 4-byte rows would exceed the register budget: four)
+  const int u = t.sched.unroll <= 1 ? 1 : t.sched.unroll <= 2 ? 2 : t.sched.unroll <= 4 || RB == 4 ? 4 : 8;
+  switch (u) {
+    case 1: nt ? F::template go<RB, 1, true>(t, s) : F::template go<RB, 1, false>(t, s); break;
+    case 2: nt ? F::template go<RB, 2, true>(t, s) : F::template go<RB, 2, false>(t, s); break;
+    case 4: nt ? F::template go<RB, 4, true>(t, s) : F::template go<RB, 4, false>(t, s); break;
+    default: nt ? F::template go<RB, 8, true>(t, s) : F::template go<RB, 8, false>(t, s); break;
+  }
+}
+
+template <class F>
+void vec_launch(const LaunchTable& t, hipStream_t s) {
+  if (t.row_bytes == 8) vec_by_unroll<F, 8>(t, s);
+  else vec_by_unroll<F, 4>(t, s);
+}
+
 }  // namespace
 }  // namespace kern
 
 void launch_gather_kernels(const LaunchTable& t, hipStream_t s) {
   using namespace kern;
+  if (t.vec16) {
+    switch (t.tag) {
+      case TAG_PACK: vec_launch<k_pack_vgo>(t, s); return;
+      case TAG_REDIST: vec_launch<k_redist_vgo>(t, s); return;
+      case TAG_UNPACK: vec_launch<k_unpack_vgo>(t, s); return;
+      default: break;  // the simulated transfer keeps its fixed variants
+    }
+  }
   switch (t.tag) {
     case TAG_PACK: by_vec<k_pack_go>(t, s); break;
     case TAG_REDIST: by_vec<k_redist_go>(t, s); break;

@@ -245,70 +245,134 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
 }
 
 // ---------------------------------------------------------------------------
-// Pull of 8-byte rows, two rows per lane: rows 2p and 2p + 1 of a tile take
-// one 8-byte load of their index pair, two 8-byte row loads and one 16-byte
-// store (half the index and store instructions of one row per lane; 8-byte
-// rows are bound by memory requests, not bytes).  The table builder enables
-// it only when every job's destination is 16-byte aligned, its index list
-// 8-byte aligned, the tile size even and no job uses an LDS window; a job's
-// odd last row is a half pair (one index, one 8-byte store).
+// Pull of short rows (RB = 4 or 8 bytes), 16 bytes of rows per lane: a group
+// of V = 16 / RB consecutive rows takes one V-wide load of its indices, V
+// row reads and one 16-byte store, so a wavefront's index loads and stores
+// are single coalesced streams (short rows are bound by memory requests and
+// by the latency of the index stream, not by bytes).  Each lane handles U
+// groups per pass, their index loads issued together; a job with an LDS
+// source window (win_rows > 0) has it staged by the workgroup once (16-byte
+// loads of its aligned interior, 4-byte loads of its ragged ends) while the
+// first pass's indices are in flight, and rows inside it are read from LDS,
+// the others from global memory.  Groups start at the first row whose
+// destination is 16-byte aligned; the table builder enables this form only
+// where every job's index list is congruent with its destination (the same
+// first row aligns the index vector loads), so the rows before that first
+// group and after the last one (fewer than V each) go one per lane.
 // ---------------------------------------------------------------------------
-template <int U, bool NT>
-__device__ __forceinline__ void gather_pair_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
-                                                 int njobs, int64_t ntiles, int tile_rows) {
-  using R8 = typename RawVec<8>::type;
-  using R16 = typename RawVec<16>::type;
+template <int RB> struct IdxVec;
+template <> struct IdxVec<8> { using type = i32x2; };
+template <> struct IdxVec<4> { using type = int __attribute__((ext_vector_type(4))); };
+
+template <int RB>
+__device__ __forceinline__ u32x4 pack16(const typename RawVec<RB>::type (&v)[16 / RB]) {
+  if constexpr (RB == 8) return u32x4{v[0].x, v[0].y, v[1].x, v[1].y};
+  else return u32x4{v[0], v[1], v[2], v[3]};
+}
+
+template <int RB, int U, bool NT>
+__device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
+                                                int njobs, int64_t ntiles, int tile_rows) {
+  constexpr int V = 16 / RB;
+  using R = typename RawVec<RB>::type;
+  using IV = typename IdxVec<RB>::type;
+  extern __shared__ __align__(16) unsigned char s_dyn[];
   int64_t t0, t1;
   tile_range(ntiles, &t0, &t1);
   if (t0 >= t1) return;
   int j = find_job(ts, njobs, t0);
+  int staged = -1;
+  uint32_t lds_a = 0;  // LDS byte of the staged window's first row (0..15)
+  const int bd = blockDim.x, tid = threadIdx.x;
   for (int64_t t = t0; t < t1; ++t) {
     while (t >= ts[j + 1]) ++j;
-    const R8* __restrict__ src = reinterpret_cast<const R8*>(jobs[j].src);
+    const char* __restrict__ src = jobs[j].src;
     char* __restrict__ dst = jobs[j].dst;
     const int32_t* __restrict__ idx = jobs[j].idx;
     const int64_t nrows = jobs[j].nrows;
-    const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;  // even
+    const int32_t win_lo = (int32_t)jobs[j].win_lo;
+    const uint32_t win_rows = (uint32_t)jobs[j].win_rows;
+    const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
-    const int64_t p0 = r0 >> 1, p1 = (r1 + 1) >> 1;  // pairs of the tile
-    for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)blockDim.x * U) {
-      int64_t s0[U], s1[U];
+    // first row of the tile whose destination is 16-byte aligned
+    const int64_t head = (int64_t)(((16 - ((uintptr_t)(dst + r0 * RB) & 15)) & 15) / RB);
+    const int64_t a = min(r0 + head, r1);
+    const int64_t ng = (r1 - a) / V;  // groups of the tile
+    const int64_t tail0 = a + ng * V;
+    const int nh = (int)(a - r0), ne = nh + (int)(r1 - tail0);  // rows outside the groups: < V before, < V after
+    const bool use_win = win_rows > 0 && idx != nullptr;
+    // this lane's row outside the groups (if any): its index is loaded first
+    const bool has_edge = tid < ne;
+    const int64_t er = tid < nh ? r0 + tid : tail0 + (tid - nh);
+    int32_t esr = 0;
+    if (has_edge) esr = idx ? idx[er] : (int32_t)er;
+    // a row's value: from the staged window when it lies there, else global memory
+    auto read_row = [&](int32_t sr) -> R {
+      const uint32_t w = (uint32_t)(sr - win_lo);
+      if (use_win && w < win_rows) return *reinterpret_cast<const R*>(s_dyn + lds_a + w * (uint32_t)RB);
+      return *reinterpret_cast<const R*>(src + (int64_t)sr * RB);
+    };
+    // passes of U groups per lane (a tile is usually one pass)
+    for (int64_t g0 = 0; g0 == 0 || g0 < ng; g0 += (int64_t)bd * U) {
+      IV iv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        // lanes past the tile's end redo its last pair (valid loads)
-        const int64_t p = min(base + (int64_t)u * blockDim.x, p1 - 1);
-        if (2 * p + 1 < r1) {
+        // lanes past the last group reload it (valid loads); stores are predicated
+        const int64_t g = min(g0 + tid + (int64_t)u * bd, max(ng - 1, (int64_t)0));
+        if (ng > 0) {
           if (idx) {
-            const i32x2 ip = ldv<i32x2, NT>(reinterpret_cast<const i32x2*>(idx) + p);
-            s0[u] = ip.x;
-            s1[u] = ip.y;
+            iv[u] = ldv<IV, NT>(reinterpret_cast<const IV*>(idx + a) + g);
           } else {
-            s0[u] = 2 * p;
-            s1[u] = 2 * p + 1;
-          }
-        } else {
-          s0[u] = idx ? (int64_t)ldv<int32_t, NT>(idx + 2 * p) : 2 * p;
-          s1[u] = s0[u];
-        }
-      }
-      R8 a[U], b[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        a[u] = src[s0[u]];
-        b[u] = src[s1[u]];
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t p = base + (int64_t)u * blockDim.x;
-        if (p < p1) {
-          if (2 * p + 1 < r1) {
-            const R16 w = {a[u].x, a[u].y, b[u].x, b[u].y};
-            stv<R16, NT>(reinterpret_cast<R16*>(dst) + p, w);
-          } else {
-            stv<R8, NT>(reinterpret_cast<R8*>(dst) + 2 * p, a[u]);
+            for (int k = 0; k < V; ++k) iv[u][k] = (int)(a + g * V + k);
           }
         }
       }
+      if (g0 == 0 && use_win) {
+        if (staged != j) {
+          if (staged >= 0) __syncthreads();  // every lane is done with the previous window
+          const uintptr_t A = (uintptr_t)(src + (int64_t)win_lo * RB), B = A + (uintptr_t)win_rows * RB;
+          const uintptr_t base = A & ~(uintptr_t)15;
+          const uintptr_t A16 = (A + 15) & ~(uintptr_t)15, B16 = B & ~(uintptr_t)15;
+          const int nv = B16 > A16 ? (int)((B16 - A16) >> 4) : 0;
+          const u32x4* __restrict__ gp = reinterpret_cast<const u32x4*>(A16);
+          u32x4* sp = reinterpret_cast<u32x4*>(s_dyn + (A16 - base));
+          constexpr int UW = 4;  // staging loads in flight per lane
+          for (int i0 = tid; i0 < nv; i0 += bd * UW) {
+            u32x4 w[UW];
+#pragma unroll
+            for (int u = 0; u < UW; ++u)
+              if (i0 + u * bd < nv) w[u] = gp[i0 + u * bd];
+#pragma unroll
+            for (int u = 0; u < UW; ++u)
+              if (i0 + u * bd < nv) sp[i0 + u * bd] = w[u];
+          }
+          // ragged ends: 4-byte words in [A, min(A16, B)) and [max(B16, A16), B)
+          if (tid < 8) {
+            const uintptr_t w = tid < 4 ? A + 4 * (uintptr_t)tid : max(B16, A16) + 4 * (uintptr_t)(tid - 4);
+            const bool ok = tid < 4 ? (w < A16 && w < B) : (w < B);
+            if (ok) *reinterpret_cast<unsigned int*>(s_dyn + (w - base)) = *reinterpret_cast<const unsigned int*>(w);
+          }
+          lds_a = (uint32_t)(A - base);
+          staged = j;
+        }
+        __syncthreads();  // the window is visible to every lane
+      }
+      R v[U][V];
+      R ev;
+      if (g0 == 0 && has_edge) ev = read_row(esr);
+      if (ng > 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int k = 0; k < V; ++k) v[u][k] = read_row(iv[u][k]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t g = g0 + tid + (int64_t)u * bd;
+          if (g < ng) stv<u32x4, NT>(reinterpret_cast<u32x4*>(dst + a * RB) + g, pack16<RB>(v[u]));
+        }
+      }
+      if (g0 == 0 && has_edge) stv<R, NT>(reinterpret_cast<R*>(dst + er * RB), ev);
     }
     signal_tile(jobs[j].ready, r1 - r0);
   }

@@ -174,6 +174,16 @@ Sched default_sched(int kind, int row_bytes) {
     s.blocks_per_cu = kOneShotBpc;
     s.unroll = 2;
   }
+  // gathers of 4- and 8-byte rows: 16-byte row groups per lane, one
+  // workgroup of 512 lanes per (up to) 16384-row tile, the job's window (if
+  // it has one) staged once per tile while the tile's indices are in flight
+  if (kind == KIND_GATHER && (row_bytes == 4 || row_bytes == 8)) {
+    s.pair_rows = 1;
+    s.tile_rows = 16384;
+    s.block_threads = 512;
+    s.blocks_per_cu = kOneShotBpc;
+    s.unroll = 4;
+  }
   return s;
 }
 
@@ -185,7 +195,7 @@ Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
   if (p->blocks_per_cu > 0) s.blocks_per_cu = p->blocks_per_cu;
   s.nontemporal = p->nontemporal ? 1 : 0;
   s.per_neighbor = p->per_neighbor ? 1 : 0;
-  if (p->unroll > 0) s.unroll = p->unroll <= 1 ? 1 : (p->unroll == 2 ? 2 : 4);
+  if (p->unroll > 0) s.unroll = p->unroll <= 1 ? 1 : p->unroll == 2 ? 2 : p->unroll <= 4 ? 4 : 8;
   if (p->push_pack == 1) s.push_pack = 1;
   else if (p->push_pack == 2) s.push_pack = 0;
   if (p->lds_window == 1) s.lds_window = 1;
@@ -814,6 +824,22 @@ static int launch_graph(hx_batch* b, int which, hipStream_t s) {
   return HX_SUCCESS;
 }
 
+extern "C" int hx_batch_set_sched(hx_batch* b, int phase, const hx_sched* sched) {
+  if (!b || !sched) return fail(HX_ERR_ARG, "null argument");
+  if (phase < 0 || phase > 3) return fail(HX_ERR_ARG, "bad phase %d", phase);
+  if (b->active) return fail(HX_ERR_STATE, "batch is active");
+  const int kind = phase == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
+  const Sched old = b->sched[phase];
+  b->sched[phase] = resolve_sched(sched, kind, (int)b->row_bytes);
+  if (phase == PH_PACK && batch_has_ready(b)) b->sched[PH_PACK].push_pack = 0;
+  const int rc = batch_prepare(b);
+  if (rc != HX_SUCCESS) {
+    b->sched[phase] = old;  // keep the batch usable with its previous schedule
+    (void)batch_prepare(b);
+  }
+  return rc;
+}
+
 extern "C" int hx_batch_set_replay(hx_batch* b, int mode) {
   if (!b) return fail(HX_ERR_ARG, "null batch");
   if (mode != HX_REPLAY_GRAPH && mode != HX_REPLAY_DIRECT) return fail(HX_ERR_ARG, "bad replay mode %d", mode);
@@ -1061,6 +1087,27 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
       }
     };
     consider(best);
+    // seeds for gathers of 4- and 8-byte rows: 16-byte row groups per lane,
+    // one-shot grids, with whole-job LDS windows (sources in a known window)
+    // and without (measured best on the random-matrix exchange); the
+    // stage-by-stage search below refines from the fastest
+    if (ph != PH_BWD && (rb == 4 || rb == 8) && !(ph == PH_PACK && best.push_pack)) {
+      for (int win : {1, 0})
+        for (int bt : {256, 512})
+          for (int nt : {0, 1}) {
+            Sched c = best;
+            c.pair_rows = 1;
+            c.lds_window = win;
+            c.tile_rows = win ? 16384 : 4096;
+            c.block_threads = bt;
+            c.blocks_per_cu = kOneShotBpc;
+            c.unroll = 4;
+            c.nontemporal = nt;
+            c.per_neighbor = 0;
+            c.push_pack = 0;
+            consider(c);
+          }
+    }
     // stage 1: work per tile, rows in flight, pull vs push (pack), LDS
     // source windows and two rows per lane (gathers); stage 2: launch shape
     // (persistent or one-shot grid, workgroup size) and streaming hints;
@@ -1069,14 +1116,15 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     auto tile_stage = [&]() {
       const Sched s0 = best;
       for (int tf : {1, 2, 4, 8, 16, 32})
-        for (int u : {1, 2, 4})
+        for (int u : {1, 2, 4, 8})
           for (int push : {0, 1})
             for (int win : {0, 1})
               for (int pair : {0, 1}) {
                 if (push && (ph != PH_PACK || batch_has_ready(b))) continue;
                 if (win && push) continue;
-                // two rows per lane: pull gathers of 8-byte rows without windows
-                if (pair && (b->row_bytes != 8 || win || push || ph == PH_BWD)) continue;
+                // 16-byte row groups per lane: pull gathers of 4- or 8-byte rows
+                if (pair && ((b->row_bytes != 8 && b->row_bytes != 4) || push || ph == PH_BWD)) continue;
+                if (u == 8 && !pair) continue;  // eight per lane: row groups only
                 Sched c = s0;
                 c.tile_rows = std::max(16, base * tf / 8);
                 c.unroll = u;
@@ -1097,7 +1145,7 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
               // (gathers: LDS windows again with each launch shape, where the
               // occupancy they allow depends on the workgroup size)
               if (bt == 1024 && ph == PH_PACK && s1.push_pack) continue;  // push pack: at most 512 lanes
-              if (flip && (ph == PH_BWD || (ph == PH_PACK && s1.push_pack) || s1.pair_rows)) continue;
+              if (flip && (ph == PH_BWD || (ph == PH_PACK && s1.push_pack))) continue;
               Sched c = s1;
               c.lds_window = flip ? !s1.lds_window : s1.lds_window;
               c.blocks_per_cu = bpc;
@@ -1111,10 +1159,11 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     // tile (the stage-by-stage search can stop at a near tie between them)
     {
       const Sched s3 = best;
-      for (int u : {1, 2, 4})
+      for (int u : {1, 2, 4, 8})
         for (int bpc : {2, 4, 8, kOneShotBpc})
           for (int bt : {256, 512, 1024}) {
             if (bt == 1024 && ph == PH_PACK && s3.push_pack) continue;  // push pack: at most 512 lanes
+            if (u == 8 && !s3.pair_rows) continue;
             Sched c = s3;
             c.unroll = u;
             c.blocks_per_cu = bpc;

@@ -55,7 +55,15 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
                 (True, dict(push_pack=2, lds_window=2, pair_rows=1, blocks_per_cu=1 << 20)),
                 ("direct", None), ("direct", dict(push_pack=1, tile_rows=40, blocks_per_cu=1 << 20)),
                 (False, dict(push_pack=2, lds_window=1, block_threads=1024, blocks_per_cu=2, tile_rows=300)),
-                (False, dict(push_pack=1, pair_rows=1, block_threads=1024, blocks_per_cu=1 << 20))]
+                (False, dict(push_pack=1, pair_rows=1, block_threads=1024, blocks_per_cu=1 << 20)),
+                # short rows in 16-byte groups per lane with LDS windows
+                (False, dict(push_pack=2, lds_window=1, pair_rows=1, tile_rows=50, unroll=8)),
+                (True, dict(push_pack=2, lds_window=1, pair_rows=1, block_threads=1024, blocks_per_cu=2,
+                            tile_rows=333, unroll=2)),
+                ("direct", dict(push_pack=2, lds_window=1, pair_rows=1, blocks_per_cu=1 << 20, tile_rows=4096,
+                                unroll=4, nontemporal=1)),
+                (False, dict(push_pack=2, lds_window=1, pair_rows=1, block_threads=256, blocks_per_cu=1,
+                             tile_rows=7, unroll=1))]
     ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
     out = OM.forward_all([D.plan(r, variant) for r in range(R)], xh, rs) if full_stages else None
     for plain_launch, sched in variants:
@@ -86,7 +94,7 @@ def test_world_tiny(case, variant):
     n, R, mx, pf, seed, uneven, ppn = case
     say("world tiny", case, variant)
     rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
-    for ncols, dt in ((1, "f64"), (3, "f32"), (16, "f64")):
+    for ncols, dt in ((1, "f64"), (1, "f32"), (3, "f32"), (16, "f64")):
         check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dt)
 
 
@@ -123,8 +131,19 @@ def test_world_random_rows_full_size(dtype_name, variant):
         xh = xh.astype(np.float32)
     plan = gpu_plan(rs, rp, cols, 128, variant)
     H = sum(h.size for h in halos)
+    want = xh[np.concatenate(halos)]
+    # default schedule; short rows in 16-byte groups per lane with LDS windows
+    # (one-shot and persistent grids) and without
+    for sched in (None, dict(pair_rows=1, lds_window=1, unroll=8, tile_rows=16384, block_threads=1024,
+                             blocks_per_cu=1 << 20, push_pack=2),
+                  dict(pair_rows=1, lds_window=1, unroll=2, tile_rows=3000, block_threads=512, blocks_per_cu=2,
+                       push_pack=2),
+                  dict(pair_rows=1, lds_window=2, unroll=4, tile_rows=2048, push_pack=2, nontemporal=1)):
+        say("  schedule", sched)
+        b, halo = run_world(plan, dev(xh), H, sched=sched)
+        assert bits_equal(host(halo), want)
+        b.free()
     b, halo = run_world(plan, dev(xh), H)
-    assert bits_equal(host(halo), xh[np.concatenate(halos)])
     if variant == "locality3":   # one stage-1 message per node pair that needs one
         inter = 0
         for r in range(4096):
@@ -197,5 +216,44 @@ def test_launch_phase_matches_graphs(variant):
     P.hx_batch_start(b)
     with pytest.raises(P.HXError):
         P.hx_batch_launch_phase(b, 0)
+    P.hx_batch_wait(b)
+    b.free()
+
+
+def test_set_sched_applies_and_rejects():
+    """hx_batch_set_sched: a phase's schedule is applied (and read back), the
+    results stay bit-exact, and an invalid schedule leaves the previous one."""
+    need_gpu()
+    import torch
+    n, R, mx, pf, seed, uneven, ppn = CASES[4]
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    H = sum(h.size for h in halos)
+    xh = uniform_pm1(seed, n).reshape(n, 1)
+    plan = gpu_plan(rs, rp, cols, ppn, "locality")
+    b, halo = run_world(plan, dev(xh), H)
+    want = xh[np.concatenate(halos)]
+    s1 = dict(tile_rows=24, block_threads=256, blocks_per_cu=3, unroll=2, pair_rows=1, lds_window=1)
+    for ph in (0, 1, 2):
+        P.hx_batch_set_sched(b, ph, s1)
+        got = P.hx_batch_get_sched(b, ph)
+        assert (got["tile_rows"], got["block_threads"], got["blocks_per_cu"], got["unroll"], got["pair_rows"],
+                got["lds_window"]) == (24, 256, 3, 2, 1, 1)
+    halo.fill_(float("nan"))
+    P.hx_batch_start(b)
+    P.hx_batch_wait(b)
+    assert bits_equal(host(halo), want)
+    with pytest.raises(P.HXError) as e:
+        P.hx_batch_set_sched(b, 1, dict(block_threads=300))
+    assert e.value.code == P.HX_ERR_ARG
+    assert P.hx_batch_get_sched(b, 1)["block_threads"] == 256
+    halo.fill_(float("nan"))
+    P.hx_batch_start(b)
+    P.hx_batch_wait(b)
+    assert bits_equal(host(halo), want)
+    P.hx_batch_start(b)
+    with pytest.raises(P.HXError) as e:
+        P.hx_batch_set_sched(b, 0, s1)
+    assert e.value.code == P.HX_ERR_STATE
     P.hx_batch_wait(b)
     b.free()
