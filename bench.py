@@ -1,20 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark of the halo-exchange buffer engine on one MI355X.
 
-Default workload ("batched256"): 256 independent persistent exchange plans,
+Headline workload ("batched256"): 256 independent persistent exchange plans,
 halo sizes log-uniform in [1e3, 1e6) rows, 1..4096 neighbors, 16 FP64
 columns per row.  One step = Start + Wait of all plans (pack, unpack) plus
 the backward of the pack (fixed-order transpose sum), each phase one
-multi-job kernel replayed from a hipGraph.  The same work as one launch per
-plan per phase ("plain") is timed beside it.
+multi-job kernel replayed from a hipGraph (or launched directly, as tuned).
+The same work as one launch per plan per phase ("plain") is timed beside it.
 
-Other workloads (``--workload``): random_rows / random_rows_f32 /
-random_rows_3step (2^22 x 32 random matrix, 4096 ranks, 2-step or 3-step
-locality-aware plan, every rank batched, one FP64 / FP32 column; forward
-step, the staged backward reported aside), grid3d
-(27-point 128^3, 512 ranks), grid2d (5-point 512^2, 16 ranks), diff64
-(random-matrix plain plan, 64 FP32 features, forward + backward), copy (the
-1 GiB calibration copy for the PMC scale factors).
+With the headline workload the line also carries ``configs``: every other
+workload measured the same way (tuned, warm back-to-back steps, a cold
+median with the caches flushed before each step, each kernel alone, the
+dominant kernel against the HBM roofline):
+
+* random_rows / random_rows_f32 / random_rows_3step: 2^22 x 32 random
+  matrix, 4096 ranks, 128 per node, 2-step or 3-step locality-aware plan,
+  every rank batched, one FP64 / FP32 column (forward step; the staged
+  backward reported aside);
+* rank1511: the random matrix's rank with the most neighbors alone (one
+  persistent request from the locality plan; warm, microseconds);
+* diff64: the random matrix's plain plan with 64 FP32 features, forward +
+  backward, as batch calls and through the autograd Function;
+* grid3d_diff64: the 27-point 128^3 decomposition's plain plan with 64 FP32
+  features, forward + backward;
+* grid3d, grid2d: the two stencils' locality plans, one FP64 column.
+
+``--workload`` runs one of them alone as the headline (``copy`` is the 1 GiB
+calibration copy for the PMC scale factors).  ``--sched-json`` applies
+recorded schedules instead of tuning (per phase, as hx_batch_get_sched
+reports them), ``--replay`` fixes the replay mode.
 
 Prints one JSON line (rank 0, one GPU).
 """
@@ -66,7 +80,9 @@ def read_traffic(kernel: str, workload: str):
 
 
 # ---------------------------------------------------------------------------
-# Workloads
+# Workloads: each setup returns a dict with the batch ("batch"), the phases
+# of its timed step ("phases"), its configuration ("cfg"), the arithmetic
+# dtype and whatever must stay alive ("keep").
 # ---------------------------------------------------------------------------
 def setup_batched(args, torch, P):
     import numpy as np
@@ -97,12 +113,8 @@ def setup_batched(args, torch, P):
     torch.cuda.synchronize()
     log(f"setup: {nplans} plans, sum h = {sum(m['h'] for m in members)}, {time.time() - t0:.1f}s")
     batch = P.hx_batch_init([m["req"] for m in members])
-    if not args.no_tune:
-        t0 = time.time()
-        P.hx_batch_tune(batch)
-        torch.cuda.synchronize()
-        log(f"tuned in {time.time() - t0:.1f}s: " + json.dumps([P.hx_batch_get_sched(batch, ph) for ph in range(4)]))
-    # correctness of a sampled member against the oracle before timing
+    tune(args, torch, P, batch, "batched256")
+    # correctness of sampled members against the oracle before timing
     P.hx_batch_start(batch)
     P.hx_batch_wait(batch)
     P.hx_batch_backward(batch)
@@ -121,8 +133,7 @@ def setup_batched(args, torch, P):
     cfg = {"workload": "batched256: 256 independent plans, halo 1e3..1e6 rows (log-uniform), "
                        "1..4096 neighbors, 16 x FP64 columns (128 B rows); pack+unpack+backward",
            "plans": nplans, "ncols": C, "rows_total": int(sum(m["h"] for m in members))}
-    return dict(batch=batch, members=members, host=host_keep, dtype="f64", cfg=cfg, phases=(0, 2, 3),
-                keep=members)
+    return dict(batch=batch, host=host_keep, dtype="f64", cfg=cfg, phases=(0, 2, 3), keep=members)
 
 
 def setup_copy(args, torch, P):
@@ -143,26 +154,45 @@ def setup_copy(args, torch, P):
     torch.cuda.synchronize()
     assert torch.equal(halo, P.req_arena_view(req, P.HX_ARENA_RECV, C, dt))
     cfg = {"workload": "copy calibration: identity unpack of a 1 GiB arena (128 B rows)", "bytes_copied": rows * C * 8}
-    return dict(batch=batch, members=[req], host=[], dtype="f64", cfg=cfg, phases=(0, 2, 3),
-                keep=(req, x, halo, g_x, topo))
+    return dict(batch=batch, host=[], dtype="f64", cfg=cfg, phases=(0, 2, 3), keep=(req, x, halo, g_x, topo))
+
+
+WORLD_DESC = {
+    "random_rows": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality 2-step, all ranks batched, "
+                   "1 x FP64",
+    "random_rows_f32": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality 2-step, all ranks "
+                       "batched, 1 x FP32",
+    "random_rows_3step": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality 3-step (one message per "
+                         "node pair), all ranks batched, 1 x FP64",
+    "grid3d": "27-point 128^3, 512 ranks, 64/node, locality 2-step, all ranks, 1 x FP64",
+    "grid2d": "5-point 512^2, 16 ranks, 4/node, locality 2-step, all ranks, 1 x FP64",
+    "diff64": "random 2^22 x 32, 4096 ranks, plain plan, 64 x FP32 features, forward halo gather + fixed-order "
+              "transpose-sum backward",
+    "grid3d_diff64": "27-point 128^3, 512 ranks, plain plan, 64 x FP32 features, forward halo gather + "
+                     "fixed-order transpose-sum backward",
+}
+
+
+def world_structure(name):
+    from workloads import equal_row_starts, grid2d_5pt, grid3d_27pt, random_rows
+    if name.startswith("random_rows") or name in ("diff64", "rank1511"):
+        rp, cols = random_rows()
+        return equal_row_starts(1 << 22, 4096), 128, rp, cols
+    if name.startswith("grid3d"):
+        rp, cols = grid3d_27pt()
+        return equal_row_starts(128 ** 3, 512), 64, rp, cols
+    rp, cols = grid2d_5pt()
+    return equal_row_starts(512 * 512, 16), 4, rp, cols
 
 
 def setup_world(args, torch, P, name):
     import numpy as np
-    from workloads import equal_row_starts, grid2d_5pt, grid3d_27pt, random_rows, uniform_pm1, uniform_pm1_f32
+    from workloads import uniform_pm1, uniform_pm1_f32
     t0 = time.time()
-    if name in ("random_rows", "random_rows_f32", "random_rows_3step", "diff64"):
-        rp, cols = random_rows()
-        rs, ppn = equal_row_starts(1 << 22, 4096), 128
-    elif name == "grid3d":
-        rp, cols = grid3d_27pt()
-        rs, ppn = equal_row_starts(128 ** 3, 512), 64
-    else:
-        rp, cols = grid2d_5pt()
-        rs, ppn = equal_row_starts(512 * 512, 16), 4
+    rs, ppn, rp, cols = world_structure(name)
     log(f"generated {name} structure in {time.time() - t0:.1f}s")
-    variant = P.HX_PLAIN if name == "diff64" else (P.HX_LOCALITY_3STEP if name.endswith("3step")
-                                                    else P.HX_LOCALITY_2STEP)
+    plain = name in ("diff64", "grid3d_diff64")
+    variant = P.HX_PLAIN if plain else (P.HX_LOCALITY_3STEP if name.endswith("3step") else P.HX_LOCALITY_2STEP)
     rp_d, cols_d = torch.from_numpy(rp).cuda(), torch.from_numpy(cols).cuda()
     torch.cuda.synchronize()
     t0 = time.time()
@@ -173,7 +203,7 @@ def setup_world(args, torch, P, name):
     R = len(rs) - 1
     n = int(rs[-1])
     H = sum(int(P.hx_plan_field(plan, r, "halo").size) for r in range(R))
-    if name == "diff64":
+    if plain:
         C, dt = 64, torch.float32
         x = torch.from_numpy(uniform_pm1_f32(7337, n * C).reshape(n, C)).cuda()
     elif name == "random_rows_f32":
@@ -196,42 +226,78 @@ def setup_world(args, torch, P, name):
     g_halo = torch.ones_like(halo)
     g_x = torch.empty_like(x)
     # locality plans take the backward through the plan's stages (each rank-local)
-    batch = P.hx_batch_from_plan(plan, x, halo, flags=0 if variant == P.HX_PLAIN else P.HX_WORLD_STAGED_BACKWARD)
+    batch = P.hx_batch_from_plan(plan, x, halo, flags=0 if plain else P.HX_WORLD_STAGED_BACKWARD)
     P.hx_batch_bind_grad(batch, g_halo, g_x)
-    if not args.no_tune:
-        P.hx_batch_tune(batch)
-    cfg = {"workload": {"random_rows": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality "
-                                       "2-step, all ranks batched, 1 x FP64",
-                        "random_rows_f32": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality "
-                                           "2-step, all ranks batched, 1 x FP32",
-                        "random_rows_3step": "random 2^22 x 32 (70% in-block), 4096 ranks, 128/node, locality "
-                                             "3-step (one message per node pair), all ranks batched, 1 x FP64",
-                        "grid3d": "27-point 128^3, 512 ranks, 64/node, locality 2-step, all ranks, 1 x FP64",
-                        "grid2d": "5-point 512^2, 16 ranks, 4/node, locality 2-step, all ranks, 1 x FP64",
-                        "diff64": "random 2^22 x 32, 4096 ranks, plain plan, 64 x FP32 features, forward "
-                                  "halo gather + fixed-order transpose-sum backward"}[name],
-           "ranks": R, "halo_rows": H, "ncols": C, "plan_init_s": round(plan_s, 4),
+    tune(args, torch, P, batch, name)
+    cfg = {"workload": WORLD_DESC[name], "ranks": R, "halo_rows": H, "ncols": C, "plan_init_s": round(plan_s, 4),
            "internode_messages": int(sum(int(np.sum(P.hx_plan_field(plan, r, "s1_procs") // ppn != r // ppn))
                                          for r in range(R))),
            "internode_rows": int(sum(int(np.sum(P.hx_plan_field(plan, r, "s1_counts")[
                P.hx_plan_field(plan, r, "s1_procs") // ppn != r // ppn])) for r in range(R)))}
-    # the differentiation workload times forward + backward; the others are
+    # the differentiation workloads time forward + backward; the others are
     # forward (pack / redistribution / unpack) workloads, backward reported aside
-    phases = (0, 1, 2, 3) if name == "diff64" else (0, 1, 2)
+    phases = (0, 1, 2, 3) if plain else (0, 1, 2)
     cfg["step"] = "pack + redistribution + unpack" + (" + backward" if 3 in phases else "")
-    return dict(batch=batch, members=None, host=[], dtype="f64" if dt == torch.float64 else "f32", cfg=cfg,
-                phases=phases, keep=(plan, x, halo, g_halo, g_x))
+    return dict(batch=batch, host=[], dtype="f64" if dt == torch.float64 else "f32", cfg=cfg, phases=phases,
+                keep=(plan, x, halo, g_halo, g_x), plan=plan, n=n, H=H, C=C, torch_dtype=dt)
+
+
+def setup_rank(args, torch, P, rank=1511):
+    """One rank's share alone: the persistent request of the random matrix's
+    rank with the most receive neighbors, from the 2-step locality plan; its
+    receive arena holds what its peers would send (random values)."""
+    from workloads import uniform_pm1
+    rs, ppn, rp, cols = world_structure("rank1511")
+    plan = P.hx_plan_from_csr(len(rs) - 1, rs, ppn, P.HX_LOCALITY_2STEP, torch.from_numpy(rp).cuda(),
+                              torch.from_numpy(cols).cuda())
+    n_local = int(rs[rank + 1] - rs[rank])
+    H = int(P.hx_plan_field(plan, rank, "halo").size)
+    x = torch.from_numpy(uniform_pm1(7337, n_local).reshape(n_local, 1)).cuda()
+    halo = torch.empty(H, 1, dtype=torch.float64, device="cuda")
+    req = P.hx_req_from_plan(plan, rank, x, halo)
+    recv = P.req_arena_view(req, P.HX_ARENA_RECV, 1, torch.float64)
+    recv.copy_(torch.from_numpy(uniform_pm1(99, recv.shape[0]).reshape(-1, 1)).cuda())
+    batch = P.hx_batch_init([req])
+    tune(args, torch, P, batch, "rank1511")
+    cfg = {"workload": f"random 2^22 x 32, locality 2-step plan, rank {rank} alone (its own request: "
+                       f"{n_local} rows, halo {H}, 1 x FP64); warm, not an HBM figure",
+           "rank": rank, "halo_rows": H, "recv_neighbors": int(P.hx_plan_field(plan, rank, "r1_procs").size)}
+    return dict(batch=batch, host=[], dtype="f64", cfg=cfg, phases=(0, 1, 2), keep=(plan, x, halo, req, recv))
+
+
+def tune(args, torch, P, batch, name):
+    """Applies recorded schedules (--sched-json) or tunes the batch."""
+    if args.sched_json:
+        sj = json.loads(open(args.sched_json).read() if os.path.exists(args.sched_json) else args.sched_json)
+        for ph, sc in sj.items():
+            P.hx_batch_set_sched(batch, int(ph), sc)
+    elif not args.no_tune:
+        t0 = time.time()
+        P.hx_batch_tune(batch)
+        torch.cuda.synchronize()
+        log(f"{name}: tuned in {time.time() - t0:.1f}s")
+    if args.replay:
+        P.hx_batch_set_replay(batch, P.HX_REPLAY_DIRECT if args.replay == "direct" else P.HX_REPLAY_GRAPH)
 
 
 # ---------------------------------------------------------------------------
-def time_steps(torch, P, batch, steps, warmup, plain, phases):
-    """Times `steps` steps (Start + Wait [+ backward when 3 is in phases]);
-    a backward outside the step is timed afterwards for the report only."""
-    sp = torch.cuda.current_stream().cuda_stream   # passed explicitly: no stream lookup per call
+# Timing
+# ---------------------------------------------------------------------------
+def step_fns(P, plain, sp):
     fns = {0: P.hx_batch_start_plain if plain else P.hx_batch_start,
            2: P.hx_batch_wait_plain if plain else P.hx_batch_wait,
            3: P.hx_batch_backward_plain if plain else P.hx_batch_backward}
-    run = {k: (lambda b, f=f: f(b, sp)) for k, f in fns.items()}
+    return {k: (lambda b, f=f: f(b, sp)) for k, f in fns.items()}
+
+
+def time_steps(torch, P, batch, steps, warmup, plain, phases):
+    """Warm steps (Start + Wait [+ backward when 3 is in phases]): `steps`
+    steps back to back between two synchronisations (wall clock, nothing
+    else in the loop), then the same steps with events around each phase for
+    the breakdown; a backward outside the step is timed afterwards for the
+    report only."""
+    sp = torch.cuda.current_stream().cuda_stream   # passed explicitly: no stream lookup per call
+    run = step_fns(P, plain, sp)
     with_bwd = 3 in phases
     for _ in range(warmup):
         run[0](batch)
@@ -239,8 +305,15 @@ def time_steps(torch, P, batch, steps, warmup, plain, phases):
         if with_bwd:
             run[3](batch)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     t0 = time.perf_counter()
+    for _ in range(steps):
+        run[0](batch)
+        run[2](batch)
+        if with_bwd:
+            run[3](batch)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     for i in range(steps):
         ev[i][0].record()
         run[0](batch)
@@ -251,7 +324,6 @@ def time_steps(torch, P, batch, steps, warmup, plain, phases):
             run[3](batch)
         ev[i][3].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     ph = {"start": sum(e[0].elapsed_time(e[1]) for e in ev) / steps,
           "wait": sum(e[1].elapsed_time(e[2]) for e in ev) / steps,
           "backward": sum(e[2].elapsed_time(e[3]) for e in ev) / steps}
@@ -268,23 +340,139 @@ def time_steps(torch, P, batch, steps, warmup, plain, phases):
     return wall / steps * 1e3, ph
 
 
+def time_cold(torch, P, batch, phases, flush, runs=20):
+    """Median step time with the L2 and Infinity Cache flushed before each
+    step (a 1 GiB write outside the timed range), events on the stream."""
+    sp = torch.cuda.current_stream().cuda_stream
+    run = step_fns(P, False, sp)
+    ts = []
+    for i in range(runs):
+        flush.fill_(i)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        run[0](batch)
+        run[2](batch)
+        if 3 in phases:
+            run[3](batch)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
 def time_kernels(torch, P, batch, reps, phases):
-    """Average duration of each phase's kernel launched alone: events on the
-    current stream around `reps` back-to-back launches (queued faster than
-    they run, so the host's launch cost stays hidden)."""
+    """Average duration of each phase's kernel, launched alone (the same
+    launch table the step replays) in step order, events between the
+    launches, so that each kernel meets the caches its predecessors left (as
+    in the step); `reps` rounds."""
     P.hx_batch_wait(batch)
-    out = {}
     for p in phases:
         P.hx_batch_launch_phase(batch, p)
-        torch.cuda.synchronize()
-        a, c = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(reps)]
+    for i in range(reps):
+        ev[i][0].record()
+        for k, p in enumerate(phases):
             P.hx_batch_launch_phase(batch, p)
-        c.record()
-        torch.cuda.synchronize()
-        out[p] = a.elapsed_time(c) / reps
-    return out
+            ev[i][k + 1].record()
+    torch.cuda.synchronize()
+    return {p: sum(e[k].elapsed_time(e[k + 1]) for e in ev) / reps for k, p in enumerate(phases)}
+
+
+NAMES = {0: "pack", 1: "redist", 2: "unpack", 3: "backward"}
+
+
+def kernel_symbol(P, b, phase, row_bytes, staged):
+    """Symbol of a phase's kernel (as profiles name it) under the batch's schedule."""
+    sch = P.hx_batch_get_sched(b, phase)
+    if phase == 3:
+        return "k_segsum_fwd + k_segsum" if staged else "k_segsum"
+    base = {0: "k_pack", 1: "k_redist", 2: "k_unpack"}[phase]
+    if phase == 0 and sch["push_pack"] == 1:
+        return "k_pack_push"
+    if sch["pair_rows"] == 1 and row_bytes in (4, 8):
+        return base + "_vec"
+    return base
+
+
+def measure(name, S, args, torch, P, flush, plain=True):
+    """One workload's figures: warm step throughput, cold median, phase
+    breakdown, plain one-launch-per-plan form, each kernel alone and the
+    dominant kernel against the HBM roofline."""
+    b = S["batch"]
+    nbytes = {ph: P.hx_batch_bytes(b, ph) for ph in range(4)}
+    ms, ph = time_steps(torch, P, b, args.steps, args.warmup, False, S["phases"])
+    log(f"{name}: {ms:.4f} ms/step; phases (ms) {json.dumps({k: round(v, 4) for k, v in ph.items()})}")
+    cold = time_cold(torch, P, b, S["phases"], flush) if flush is not None else None
+    plain_ms = None
+    if plain:
+        plain_ms, pph = time_steps(torch, P, b, max(3, args.steps // 4), 1, True, S["phases"])
+        log(f"{name} plain: {plain_ms:.3f} ms/step; phases (ms) {json.dumps({k: round(v, 4) for k, v in pph.items()})}")
+    step_bytes = sum(v for ph_id, v in nbytes.items() if ph_id != 3 or 3 in S["phases"])
+    value = step_bytes / (ms * 1e-3) / 1e9
+    kms = time_kernels(torch, P, b, max(5, args.steps // 2), [p for p in (0, 1, 2, 3) if nbytes[p] > 0])
+    log(f"{name} kernels alone (ms): {json.dumps({NAMES[p]: round(t, 4) for p, t in kms.items()})}")
+    step_k = {p: t for p, t in kms.items() if p != 3 or 3 in S["phases"]}
+    dom_p = max(step_k, key=lambda p: step_k[p])
+    achieved = nbytes[dom_p] / (kms[dom_p] * 1e-3) / 1e9
+    row_bytes = S["cfg"].get("ncols", 16) * (8 if S["dtype"] == "f64" else 4)
+    # (a locality world's staged backward is reported aside, never the step's dominant kernel)
+    kname = kernel_symbol(P, b, dom_p, row_bytes, staged=False)
+    traffic = read_traffic(kname, name)
+    replay = P.hx_batch_get_replay(b)
+    out = {
+        "workload": S["cfg"], "value": round(value, 2), "unit": "GB/s",
+        "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
+        "ms_per_step": round(ms, 4),
+        "cold_ms_median": round(cold, 4) if cold is not None else None,
+        "cold_gbps": round(step_bytes / (cold * 1e-3) / 1e9, 2) if cold else None,
+        "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+        "kernel_ms": {NAMES[p]: round(t, 4) for p, t in kms.items()},
+        "kernel_gbps": {NAMES[p]: round(nbytes[p] / (t * 1e-3) / 1e9, 1) for p, t in kms.items()},
+        "phase_bytes": {NAMES[p]: nbytes[p] for p in range(4)},
+        "bwd_in_step": 3 in S["phases"],
+        "plain_ms_per_step": round(plain_ms, 4) if plain_ms else None,
+        "speedup_batched_vs_plain": round(plain_ms / ms, 3) if plain_ms else None,
+        "roofline": {"bound": "hbm", "kernel": f"{kname} ({NAMES[dom_p]})", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic},
+        "replay": "direct" if replay == P.HX_REPLAY_DIRECT else "graph",
+        "sched": {NAMES[p]: P.hx_batch_get_sched(b, p) for p in range(4) if nbytes[p] > 0},
+    }
+    return out, step_bytes
+
+
+def time_halo_gather(S, args, torch, P):
+    """diff64 through the autograd Function: zero-copy input (the exchange's
+    own vector), aliased output, gradient handed over in the exchange's
+    gradient buffer; the backward's returned gradient is a fresh tensor (a
+    copy, inside the timed step)."""
+    from paper_2309_07337_amd.autograd import HaloExchange, halo_gather
+    ex = HaloExchange(S["plan"], S["n"], S["H"], S["C"], dtype=S["torch_dtype"], sim_transfer=False)
+    if args.sched_json or not args.no_tune:
+        for p in (0, 2, 3):   # the schedules tuned for the batch of the same plan
+            P.hx_batch_set_sched(ex.batch, p, P.hx_batch_get_sched(S["batch"], p))
+        P.hx_batch_set_replay(ex.batch, P.hx_batch_get_replay(S["batch"]))
+    ex.x.copy_(S["keep"][1])
+    ex.g_halo.fill_(1.0)
+    x = ex.x.detach().requires_grad_(True)
+
+    def step():
+        x.grad = None
+        y = halo_gather(x, ex, copy_out=False)
+        y.backward(ex.g_halo)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    del ex, x
+    return ms
 
 
 def host_cpu():
@@ -383,12 +571,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched256",
-                    choices=["batched256", "random_rows", "random_rows_f32", "random_rows_3step", "grid3d", "grid2d",
-                             "diff64", "copy"])
+    workloads = ["batched256", "random_rows", "random_rows_f32", "random_rows_3step", "rank1511", "diff64",
+                 "grid3d_diff64", "grid3d", "grid2d", "copy"]
+    ap.add_argument("--workload", default="batched256", choices=workloads)
     ap.add_argument("--plans", type=int, default=256)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cold", action="store_true", help="skip the flushed-cache median")
+    ap.add_argument("--sched-json", default="", help="per-phase schedules to apply instead of tuning "
+                                                     "(JSON text or file: {\"0\": {...}, ...})")
+    ap.add_argument("--replay", choices=["graph", "direct"], default="")
     ap.add_argument("--cpu-plans", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     args = ap.parse_args()
@@ -396,69 +589,63 @@ def main():
         print(json.dumps({"error": "hx runs on one GPU only: one rank's share (or a batch of "
                                    "ranks) per GPU; no collectives between GPUs. Use --gpus 1."}))
         sys.exit(2)
+    import gc
     import torch
     import paper_2309_07337_amd as P
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    flush = None if args.no_cold else torch.empty(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
+
+    def setup(name):
+        if name == "batched256":
+            return setup_batched(args, torch, P)
+        args.cpu_plans = 0
+        if name == "copy":
+            return setup_copy(args, torch, P)
+        if name == "rank1511":
+            return setup_rank(args, torch, P)
+        return setup_world(args, torch, P, name)
+
     with torch.cuda.stream(stream):
-        if args.workload == "batched256":
-            S = setup_batched(args, torch, P)
-        elif args.workload == "copy":
-            args.cpu_plans = 0
-            S = setup_copy(args, torch, P)
-        else:
-            args.cpu_plans = 0
-            S = setup_world(args, torch, P, args.workload)
-        b = S["batch"]
-        nbytes = {ph: P.hx_batch_bytes(b, ph) for ph in range(4)}
-        ms, ph = time_steps(torch, P, b, args.steps, args.warmup, False, S["phases"])
-        log(f"batched: {ms:.3f} ms/step; phases (ms) {json.dumps({k: round(v, 4) for k, v in ph.items()})}")
-        plain_ms = None
-        if not args.no_plain:
-            plain_ms, pph = time_steps(torch, P, b, max(3, args.steps // 4), 1, True, S["phases"])
-            log(f"plain:   {plain_ms:.3f} ms/step; phases (ms) {json.dumps({k: round(v, 4) for k, v in pph.items()})}")
-    step_bytes = sum(v for ph_id, v in nbytes.items() if ph_id != 3 or 3 in S["phases"])
-    value = step_bytes / (ms * 1e-3) / 1e9
-    # dominant kernel: each phase's kernel timed alone (same launch
-    # table as the graphs, same stream), the longest one of the step
-    names = {0: "pack", 1: "redist", 2: "unpack", 3: "backward"}
-    with torch.cuda.stream(stream):
-        kms = time_kernels(torch, P, b, max(5, args.steps // 2), [p for p in (0, 1, 2, 3) if nbytes[p] > 0])
-    step_k = {p: t for p, t in kms.items() if p != 3 or 3 in S["phases"]}
-    dom_p = max(step_k, key=lambda p: step_k[p])
-    dom = names[dom_p]
-    achieved = nbytes[dom_p] / (kms[dom_p] * 1e-3) / 1e9
-    kname = {"pack": "k_pack", "redist": "k_redist", "unpack": "k_unpack", "backward": "k_segsum"}[dom]
-    sch = P.hx_batch_get_sched(b, dom_p)
-    row_bytes = S["cfg"].get("ncols", 16) * (8 if S["dtype"] == "f64" else 4)
-    if dom == "pack" and sch["push_pack"] == 1:
-        kname = "k_pack_push"
-    elif dom != "backward" and sch["pair_rows"] == 1 and row_bytes == 8:
-        kname += "_pair"   # 8-byte rows two per lane
-    log(f"kernels alone (ms): {json.dumps({names[p]: round(t, 4) for p, t in kms.items()})}")
-    traffic = read_traffic(kname, args.workload)
+        cpu_plans = args.cpu_plans
+        S = setup(args.workload)
+        head, step_bytes = measure(args.workload, S, args, torch, P, flush, plain=not args.no_plain)
+        if args.workload in ("diff64", "grid3d_diff64"):
+            head["through_autograd_ms_per_step"] = round(time_halo_gather(S, args, torch, P), 4)
+    args.cpu_plans = cpu_plans
     cpu = cpu_baseline(S, args.cpu_seconds) if S["host"] else None
+    head_dtype = S["dtype"]
+    del S
+    configs = {}
+    if args.workload == "batched256" and not args.no_configs:
+        for name in ("random_rows", "random_rows_f32", "random_rows_3step", "rank1511", "diff64",
+                     "grid3d_diff64", "grid3d", "grid2d"):
+            gc.collect()
+            torch.cuda.empty_cache()
+            with torch.cuda.stream(stream):
+                Sc = setup(name)
+                res, sb = measure(name, Sc, args, torch, P, None if name == "rank1511" else flush,
+                                  plain=name not in ("rank1511",) and not args.no_plain)
+                if name in ("diff64", "grid3d_diff64"):
+                    ams = time_halo_gather(Sc, args, torch, P)
+                    res["through_autograd_ms_per_step"] = round(ams, 4)
+                    res["through_autograd_gbps"] = round(sb / (ams * 1e-3) / 1e9, 2)
+            configs[name] = res
+            del Sc
     out = {
         "metric": "effective HBM GB/s (fwd pack+unpack, bwd) and % of peak; batched vs plain",
-        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": S["dtype"], "data": "synthetic (seeded SplitMix64)",
-        "config": S["cfg"],
-        "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
-        "phases_ms": {k: round(v, 4) for k, v in ph.items()},
-        "kernel_ms": {names[p]: round(t, 4) for p, t in kms.items()},
-        "phase_bytes": {"pack": nbytes[0], "redist": nbytes[1], "unpack": nbytes[2], "backward": nbytes[3]},
-        "fwd_gbps": round((nbytes[0] + nbytes[1] + nbytes[2]) / ((ph["start"] + ph["wait"]) * 1e-3) / 1e9, 2),
-        "bwd_gbps": round(nbytes[3] / (ph["backward"] * 1e-3) / 1e9, 2) if ph["backward"] > 0 else None,
-        "bwd_in_step": 3 in S["phases"],
-        "plain_ms_per_step": round(plain_ms, 4) if plain_ms else None,
-        "plain_gbps": round(step_bytes / (plain_ms * 1e-3) / 1e9, 2) if plain_ms else None,
-        "speedup_batched_vs_plain": round(plain_ms / ms, 3) if plain_ms else None,
-        "roofline": {"bound": "hbm", "kernel": f"{kname} ({dom})", "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic},
-        "cpu_baseline": cpu,
+        "value": head["value"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": head_dtype, "data": "synthetic (seeded SplitMix64)",
+        "config": head.pop("workload"),
     }
+    head.pop("value")
+    head.pop("unit")
+    head.pop("ms_per_step")
+    out.update(head)
+    out["cpu_baseline"] = cpu
+    if configs:
+        out["configs"] = configs
     print(json.dumps(out), flush=True)
 
 

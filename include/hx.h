@@ -93,8 +93,7 @@ typedef struct {
   int nontemporal;    /* 1: streaming (non-temporal) loads/stores of index and output */
   int per_neighbor;   /* see above */
   int unroll;         /* rows per lane in flight: 1, 2 or 4 (0 = default);
-                         with pair_rows = 1, 16-byte row groups per lane:
-                         1, 2, 4 or 8 */
+                         with pair_rows = 1, 16-byte row groups per lane */
   int push_pack;      /* pack phase only: 1 = push form (walk the transpose of
                          the pack map, read each source row once and write it
                          to all its slots); 2 = pull form (gather per slot);

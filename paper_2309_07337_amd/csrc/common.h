@@ -131,7 +131,7 @@ struct Sched {
   int blocks_per_cu = 0;
   int nontemporal = 0;
   int per_neighbor = 0;
-  int unroll = 0;     // rows per lane in flight: 1, 2, 4 (16-byte row groups per lane: also 8)
+  int unroll = 0;     // rows (or 16-byte row groups) per lane in flight: 1, 2, 4
   int push_pack = 0;  // pack in push form (read each source row once)
   int lds_window = 0; // gathers stage each job's source window in LDS
   int pair_rows = 0;  // gathers of 4- or 8-byte rows: 16 bytes of rows per lane (2 or 4 rows)

@@ -69,17 +69,14 @@ void transfer_shape(const LaunchTable& t, hipStream_t s) {
 }
 
 // Short rows, 16 bytes per lane (the table builder set t.vec16): rows of 4
-// or 8 bytes, U groups per lane in {1, 2, 4, 8}.
+// or 8 bytes, U groups per lane in {1, 2, 4} (more would spill registers).
 template <class F, int RB>
 void vec_by_unroll(const LaunchTable& t, hipStream_t s) {
   const bool nt = t.sched.nontemporal != 0;
-  // (eight groups of 4-byte rows would exceed the register budget: four)
-  const int u = t.sched.unroll <= 1 ? 1 : t.sched.unroll <= 2 ? 2 : t.sched.unroll <= 4 || RB == 4 ? 4 : 8;
-  switch (u) {
+  switch (unroll_bucket(t.sched.unroll)) {
     case 1: nt ? F::template go<RB, 1, true>(t, s) : F::template go<RB, 1, false>(t, s); break;
     case 2: nt ? F::template go<RB, 2, true>(t, s) : F::template go<RB, 2, false>(t, s); break;
-    case 4: nt ? F::template go<RB, 4, true>(t, s) : F::template go<RB, 4, false>(t, s); break;
-    default: nt ? F::template go<RB, 8, true>(t, s) : F::template go<RB, 8, false>(t, s); break;
+    default: nt ? F::template go<RB, 4, true>(t, s) : F::template go<RB, 4, false>(t, s); break;
   }
 }
 

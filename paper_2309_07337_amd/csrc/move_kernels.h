@@ -312,65 +312,72 @@ __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jo
       if (use_win && w < win_rows) return *reinterpret_cast<const R*>(s_dyn + lds_a + w * (uint32_t)RB);
       return *reinterpret_cast<const R*>(src + (int64_t)sr * RB);
     };
-    // passes of U groups per lane (a tile is usually one pass)
-    for (int64_t g0 = 0; g0 == 0 || g0 < ng; g0 += (int64_t)bd * U) {
-      IV iv[U];
+    // the U index vectors of a lane for the pass starting at group g0
+    // (lanes past the last group reload it: valid loads; stores are predicated)
+    auto load_idx = [&](IV (&iv)[U], int64_t g0) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        // lanes past the last group reload it (valid loads); stores are predicated
         const int64_t g = min(g0 + tid + (int64_t)u * bd, max(ng - 1, (int64_t)0));
-        if (ng > 0) {
-          if (idx) {
-            iv[u] = ldv<IV, NT>(reinterpret_cast<const IV*>(idx + a) + g);
-          } else {
+        if (idx) {
+          iv[u] = ldv<IV, NT>(reinterpret_cast<const IV*>(idx + a) + g);
+        } else {
 #pragma unroll
-            for (int k = 0; k < V; ++k) iv[u][k] = (int)(a + g * V + k);
-          }
+          for (int k = 0; k < V; ++k) iv[u][k] = (int)(a + g * V + k);
         }
       }
-      if (g0 == 0 && use_win) {
-        if (staged != j) {
-          if (staged >= 0) __syncthreads();  // every lane is done with the previous window
-          const uintptr_t A = (uintptr_t)(src + (int64_t)win_lo * RB), B = A + (uintptr_t)win_rows * RB;
-          const uintptr_t base = A & ~(uintptr_t)15;
-          const uintptr_t A16 = (A + 15) & ~(uintptr_t)15, B16 = B & ~(uintptr_t)15;
-          const int nv = B16 > A16 ? (int)((B16 - A16) >> 4) : 0;
-          const u32x4* __restrict__ gp = reinterpret_cast<const u32x4*>(A16);
-          u32x4* sp = reinterpret_cast<u32x4*>(s_dyn + (A16 - base));
-          constexpr int UW = 4;  // staging loads in flight per lane
-          for (int i0 = tid; i0 < nv; i0 += bd * UW) {
-            u32x4 w[UW];
+    };
+    IV iv[U];
+    if (ng > 0) load_idx(iv, 0);
+    if (use_win) {
+      if (staged != j) {
+        if (staged >= 0) __syncthreads();  // every lane is done with the previous window
+        const uintptr_t A = (uintptr_t)(src + (int64_t)win_lo * RB), B = A + (uintptr_t)win_rows * RB;
+        const uintptr_t base = A & ~(uintptr_t)15;
+        const uintptr_t A16 = (A + 15) & ~(uintptr_t)15, B16 = B & ~(uintptr_t)15;
+        const int nv = B16 > A16 ? (int)((B16 - A16) >> 4) : 0;
+        const u32x4* __restrict__ gp = reinterpret_cast<const u32x4*>(A16);
+        u32x4* sp = reinterpret_cast<u32x4*>(s_dyn + (A16 - base));
+        // all of a lane's staging loads in flight together (an 80 KiB window
+        // is at most 10 per lane with 512 lanes)
+        constexpr int UW = 10;
+        for (int i0 = tid; i0 < nv; i0 += bd * UW) {
+          u32x4 w[UW];
 #pragma unroll
-            for (int u = 0; u < UW; ++u)
-              if (i0 + u * bd < nv) w[u] = gp[i0 + u * bd];
+          for (int u = 0; u < UW; ++u)
+            if (i0 + u * bd < nv) w[u] = gp[i0 + u * bd];
 #pragma unroll
-            for (int u = 0; u < UW; ++u)
-              if (i0 + u * bd < nv) sp[i0 + u * bd] = w[u];
-          }
-          // ragged ends: 4-byte words in [A, min(A16, B)) and [max(B16, A16), B)
-          if (tid < 8) {
-            const uintptr_t w = tid < 4 ? A + 4 * (uintptr_t)tid : max(B16, A16) + 4 * (uintptr_t)(tid - 4);
-            const bool ok = tid < 4 ? (w < A16 && w < B) : (w < B);
-            if (ok) *reinterpret_cast<unsigned int*>(s_dyn + (w - base)) = *reinterpret_cast<const unsigned int*>(w);
-          }
-          lds_a = (uint32_t)(A - base);
-          staged = j;
+          for (int u = 0; u < UW; ++u)
+            if (i0 + u * bd < nv) sp[i0 + u * bd] = w[u];
         }
-        __syncthreads();  // the window is visible to every lane
+        // ragged ends: 4-byte words in [A, min(A16, B)) and [max(B16, A16), B)
+        if (tid < 8) {
+          const uintptr_t w = tid < 4 ? A + 4 * (uintptr_t)tid : max(B16, A16) + 4 * (uintptr_t)(tid - 4);
+          const bool ok = tid < 4 ? (w < A16 && w < B) : (w < B);
+          if (ok) *reinterpret_cast<unsigned int*>(s_dyn + (w - base)) = *reinterpret_cast<const unsigned int*>(w);
+        }
+        lds_a = (uint32_t)(A - base);
+        staged = j;
       }
+      __syncthreads();  // the window is visible to every lane
+    }
+    if (ng == 0 && has_edge) stv<R, NT>(reinterpret_cast<R*>(dst + er * RB), read_row(esr));
+    // passes of U groups per lane (a tile is usually one pass); the next
+    // pass's indices are loaded while this pass's rows are read and stored,
+    // and the lane's row outside the groups goes with the first pass
+    for (int64_t g0 = 0; g0 < ng; g0 += (int64_t)bd * U) {
       R v[U][V];
       R ev;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < V; ++k) v[u][k] = read_row(iv[u][k]);
       if (g0 == 0 && has_edge) ev = read_row(esr);
-      if (ng > 0) {
+      const int64_t gn = g0 + (int64_t)bd * U;
+      if (gn < ng) load_idx(iv, gn);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int k = 0; k < V; ++k) v[u][k] = read_row(iv[u][k]);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t g = g0 + tid + (int64_t)u * bd;
-          if (g < ng) stv<u32x4, NT>(reinterpret_cast<u32x4*>(dst + a * RB) + g, pack16<RB>(v[u]));
-        }
+      for (int u = 0; u < U; ++u) {
+        const int64_t g = g0 + tid + (int64_t)u * bd;
+        if (g < ng) stv<u32x4, NT>(reinterpret_cast<u32x4*>(dst + a * RB) + g, pack16<RB>(v[u]));
       }
       if (g0 == 0 && has_edge) stv<R, NT>(reinterpret_cast<R*>(dst + er * RB), ev);
     }

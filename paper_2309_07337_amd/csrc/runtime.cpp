@@ -195,7 +195,7 @@ Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
   if (p->blocks_per_cu > 0) s.blocks_per_cu = p->blocks_per_cu;
   s.nontemporal = p->nontemporal ? 1 : 0;
   s.per_neighbor = p->per_neighbor ? 1 : 0;
-  if (p->unroll > 0) s.unroll = p->unroll <= 1 ? 1 : p->unroll == 2 ? 2 : p->unroll <= 4 ? 4 : 8;
+  if (p->unroll > 0) s.unroll = p->unroll <= 1 ? 1 : (p->unroll == 2 ? 2 : 4);
   if (p->push_pack == 1) s.push_pack = 1;
   else if (p->push_pack == 2) s.push_pack = 0;
   if (p->lds_window == 1) s.lds_window = 1;
@@ -1116,7 +1116,7 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     auto tile_stage = [&]() {
       const Sched s0 = best;
       for (int tf : {1, 2, 4, 8, 16, 32})
-        for (int u : {1, 2, 4, 8})
+        for (int u : {1, 2, 4})
           for (int push : {0, 1})
             for (int win : {0, 1})
               for (int pair : {0, 1}) {
@@ -1124,7 +1124,6 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
                 if (win && push) continue;
                 // 16-byte row groups per lane: pull gathers of 4- or 8-byte rows
                 if (pair && ((b->row_bytes != 8 && b->row_bytes != 4) || push || ph == PH_BWD)) continue;
-                if (u == 8 && !pair) continue;  // eight per lane: row groups only
                 Sched c = s0;
                 c.tile_rows = std::max(16, base * tf / 8);
                 c.unroll = u;
@@ -1159,11 +1158,10 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     // tile (the stage-by-stage search can stop at a near tie between them)
     {
       const Sched s3 = best;
-      for (int u : {1, 2, 4, 8})
+      for (int u : {1, 2, 4})
         for (int bpc : {2, 4, 8, kOneShotBpc})
           for (int bt : {256, 512, 1024}) {
             if (bt == 1024 && ph == PH_PACK && s3.push_pack) continue;  // push pack: at most 512 lanes
-            if (u == 8 && !s3.pair_rows) continue;
             Sched c = s3;
             c.unroll = u;
             c.blocks_per_cu = bpc;
