@@ -96,6 +96,8 @@ struct GatherJob {
   // when set: after each tile, the rows it wrote are added to *ready once
   // they are visible device-wide (a message's completion counter)
   unsigned long long* ready = nullptr;
+  // set by the table builder: every index of the job lies in its window
+  int32_t win_all = 0;
 };
 // out[i, :] = in[idx[ptr[i]], :] + in[idx[ptr[i]+1], :] + ... (ascending,
 // first term first; empty -> +0) for i < nrows.  Terms t >= split come from
@@ -172,7 +174,10 @@ struct LaunchTable {
   int vec_bytes = 0;  // 16, 8 or 4: divides row_bytes and all base pointers
   int win_bytes = 0;  // dynamic LDS of a gather table whose jobs use windows
   int val_bytes = 0;  // segmented sums: dynamic LDS term buffer (whole rows)
-  int vec16 = 0;      // gathers of 4- or 8-byte rows in 16-byte groups per lane (alignment allows it)
+  int vec16 = 0;      // gathers of 4- or 8-byte rows in 16-byte groups per lane (alignment allows it);
+                      // segmented sums of rows of one value: one row per lane
+  int vec_depth = 4;  // one-value segmented sums: terms per row loaded together (4 or 16)
+  int partial_win = 0;  // row-group gathers: some job's window misses some of its indices
   Sched sched;
   int njobs = 0;
   int64_t ntiles = 0;

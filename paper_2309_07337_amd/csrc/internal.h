@@ -63,6 +63,7 @@ struct hx_batch {
   int flags = 0;
   std::vector<hx_req*> members;
   hx::Sched sched[4];
+  bool sched_from_cache[4] = {true, true, true, true};  // no schedule given: the phase takes the tuning cache's
   hx::LaunchTable lt[4];
   std::vector<hx::LaunchTable> plain[4];
   bool plain_built[4] = {false, false, false, false};

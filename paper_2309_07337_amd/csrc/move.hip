@@ -11,11 +11,11 @@
 namespace hx {
 namespace {
 
-// bad[j] = 1 when more than half of job j's indices lie outside its source
-// window (rows outside a window are read from global memory, so a window
-// that holds few of them only costs its staging).
+// outside[j] = how many of job j's indices lie outside its source window
+// (rows outside a window are read from global memory, so a window that
+// holds few of them only costs its staging).
 __global__ void __launch_bounds__(256) k_check_windows(const GatherJob* __restrict__ jobs, int njobs,
-                                                       int32_t* __restrict__ bad) {
+                                                       int64_t* __restrict__ outside) {
   __shared__ unsigned long long s_out;
   for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
     const GatherJob g = jobs[j];
@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(256) k_check_windows(const GatherJob* __restri
     }
     if (out) atomicAdd(&s_out, out);  // LDS atomic
     __syncthreads();
-    if (threadIdx.x == 0) bad[j] = 2 * (int64_t)s_out > g.nrows ? 1 : 0;
+    if (threadIdx.x == 0) outside[j] = (int64_t)s_out;
     __syncthreads();  // s_out is reset for the next job
   }
 }
@@ -54,6 +54,15 @@ __global__ void __launch_bounds__(256) k_tile_terms(const SegSumJob* __restrict_
   }
 }
 
+// Total terms of a segmented sum's jobs: the sum of ptr[nrows] - ptr[0].
+__global__ void __launch_bounds__(256) k_term_count(const SegSumJob* __restrict__ jobs, int njobs,
+                                                    unsigned long long* __restrict__ total) {
+  unsigned long long acc = 0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < njobs; j += gridDim.x * blockDim.x)
+    acc += (unsigned long long)(jobs[j].ptr[jobs[j].nrows] - jobs[j].ptr[0]);
+  if (acc) atomicAdd(total, acc);
+}
+
 // The launch table of a single segmented-sum job written in place: the job
 // descriptor, the tile prefix {0, ntiles} and every tile's entry range (as
 // k_tile_terms), all from the kernel's arguments and the job's row pointers.
@@ -74,27 +83,32 @@ __global__ void __launch_bounds__(256) k_area_table(SegSumJob job, int64_t ntile
 }
 
 // Clears the windows of jobs that hold less than half of their indices
-// (device-side count).
+// and marks the jobs whose window holds all of them (device-side count).
 int drop_bad_windows(std::vector<GatherJob>* w) {
   std::vector<int> at;
-  for (size_t i = 0; i < w->size(); ++i)
+  for (size_t i = 0; i < w->size(); ++i) {
+    (*w)[i].win_all = 0;
     if ((*w)[i].win_rows > 0 && (*w)[i].nrows > 0) at.push_back((int)i);
+  }
   if (at.empty()) return HX_SUCCESS;
   std::vector<GatherJob> sub;
   for (int i : at) sub.push_back((*w)[i]);
-  DevMem d_jobs, d_bad;
+  DevMem d_jobs, d_out;
   HX_TRY(upload_vec(d_jobs, sub));
-  HX_TRY(d_bad.alloc(sub.size() * sizeof(int32_t)));
+  HX_TRY(d_out.alloc(sub.size() * sizeof(int64_t)));
   const int grid = (int)std::min<size_t>(sub.size(), 4096);
   hipLaunchKernelGGL(k_check_windows, dim3(grid), dim3(256), 0, 0, d_jobs.as<GatherJob>(), (int)sub.size(),
-                     d_bad.as<int32_t>());
+                     d_out.as<int64_t>());
   HX_HIP(hipGetLastError());
-  std::vector<int32_t> bad(sub.size(), 1);
-  HX_HIP(hipMemcpy(bad.data(), d_bad.p, bad.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<int64_t> outside(sub.size(), 0);
+  HX_HIP(hipMemcpy(outside.data(), d_out.p, outside.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
   for (size_t k = 0; k < at.size(); ++k) {
-    if (bad[k]) {
-      (*w)[at[k]].win_lo = 0;
-      (*w)[at[k]].win_rows = 0;
+    GatherJob& g = (*w)[at[k]];
+    if (g.idx == nullptr || 2 * outside[k] > g.nrows) {
+      g.win_lo = 0;
+      g.win_rows = 0;
+    } else {
+      g.win_all = outside[k] == 0 ? 1 : 0;
     }
   }
   return HX_SUCCESS;
@@ -117,6 +131,7 @@ int shape_table(const std::vector<J>& jobs, int kind, int dtype, int row_bytes, 
   t->dtype = dtype;
   t->row_bytes = row_bytes;
   t->sched = s0;
+  t->vec16 = 0;
   if (t->sched.tile_rows <= 0 || t->sched.block_threads <= 0 || t->sched.blocks_per_cu <= 0)
     return fail(HX_ERR_ARG, "invalid schedule (tile_rows %d, block_threads %d, blocks_per_cu %d)",
                 t->sched.tile_rows, t->sched.block_threads, t->sched.blocks_per_cu);
@@ -237,13 +252,50 @@ int build_gather_table(const std::vector<GatherJob>& jobs, int dtype, int row_by
   // (the runtime-row-size kernel form ignores windows and reads global memory)
   t->win_bytes = t->ntiles > 0 ? (int)((win_bytes + 15) / 16 * 16) : 0;
   t->vec16 = t->ntiles > 0 && vec ? 1 : 0;
+  t->partial_win = 0;
+  for (const auto& j : w)
+    if (j.nrows > 0 && j.win_rows > 0 && !j.win_all) t->partial_win = 1;
   return HX_SUCCESS;
 }
 
 // Shape of a segmented-sum table: term windows, launch shape, term buffer
 // (no device memory).
+// Shape of a segmented sum of rows of one value, one row per lane: each
+// job keeps its term window where it fits (80 KiB with the staging's
+// alignment) and lies in one input; no term buffer.
+int shape_segsum_vec_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
+                           LaunchTable* t, int tag, std::vector<SegSumJob>* kept, std::vector<int64_t>* ts) {
+  t->tag = tag;
+  std::vector<SegSumJob> w(jobs);
+  const int64_t cap = std::min<int64_t>(kWinBytes, device_lds_per_block());
+  int64_t win_bytes = 0;
+  for (auto& j : w) {
+    const int64_t hi = j.win_lo + j.win_rows;
+    const bool one_input = hi <= j.split || j.win_lo >= j.split;
+    int64_t span = 0;
+    if (j.win_rows > 0 && j.win_lo >= 0 && one_input) {
+      const char* a = j.win_lo < j.split ? j.in + j.win_lo * (int64_t)row_bytes
+                                         : j.in2 + (j.win_lo - j.split) * (int64_t)row_bytes;
+      span = j.win_rows * (int64_t)row_bytes + (int64_t)((uintptr_t)a & 15);
+    }
+    if (!s.lds_window || j.nrows <= 0 || span <= 0 || span > cap) {
+      j.win_lo = j.win_rows = 0;
+    } else {
+      win_bytes = std::max(win_bytes, span);
+    }
+  }
+  HX_TRY(shape_table(w, KIND_SEGSUM, dtype, row_bytes, s, t, align_of(w, row_bytes), kept, ts));
+  t->win_bytes = t->ntiles > 0 ? (int)((win_bytes + 15) / 16 * 16) : 0;
+  t->val_bytes = 0;
+  t->vec16 = t->ntiles > 0 ? 1 : 0;
+  t->vec_depth = 4;  // (set from the jobs' term counts when the table is uploaded)
+  return HX_SUCCESS;
+}
+
 int shape_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_bytes, const Sched& s,
                        LaunchTable* t, int tag, std::vector<SegSumJob>* kept, std::vector<int64_t>* ts) {
+  if (s.pair_rows && (row_bytes == 4 || row_bytes == 8) && (size_t)row_bytes == dtype_bytes(dtype))
+    return shape_segsum_vec_table(jobs, dtype, row_bytes, s, t, tag, kept, ts);
   t->tag = tag;
   // term windows: kept where the schedule asks for them, they fit, and they
   // lie inside one of the two inputs
@@ -288,6 +340,23 @@ int build_segsum_table(const std::vector<SegSumJob>& jobs, int dtype, int row_by
   if (t->ntiles == 0) return HX_SUCCESS;
   HX_TRY(upload_vec(t->jobs, kept));
   HX_TRY(upload_vec(t->tile_start, ts));
+  if (t->vec16) {
+    // one-value sums: 16 terms per row loaded together (one row per lane)
+    // where rows average more than three terms (the owner sums of high
+    // fan-out packs), else 4
+    int64_t rows = 0;
+    for (const auto& j : kept) rows += j.nrows;
+    DevMem d_terms;
+    HX_TRY(d_terms.alloc(sizeof(unsigned long long)));
+    HX_HIP(hipMemset(d_terms.p, 0, sizeof(unsigned long long)));
+    const int grid = (int)std::min<size_t>((kept.size() + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_term_count, dim3(grid), dim3(256), 0, 0, t->jobs.as<SegSumJob>(), t->njobs,
+                       d_terms.as<unsigned long long>());
+    HX_HIP(hipGetLastError());
+    unsigned long long terms = 0;
+    HX_HIP(hipMemcpy(&terms, d_terms.p, sizeof(terms), hipMemcpyDeviceToHost));
+    t->vec_depth = (int64_t)terms > 3 * rows ? 16 : 4;
+  }
   return fill_tile_terms(t);
 }
 

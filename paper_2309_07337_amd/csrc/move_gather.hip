@@ -15,18 +15,23 @@ namespace {
            int64_t ntiles, int tile_rows, int nv_rt, int use_win) {                            \
     gather_body<VB, NV, LPR, U, NT>(jobs, ts, njobs, ntiles, tile_rows, nv_rt, use_win);       \
   }                                                                                            \
-  template <int RB, int U, bool NT>                                                            \
+  template <int RB, int U, bool NT, bool GAS>                                                  \
   __global__ void __launch_bounds__(1024)                                                      \
       NAME##_vec(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs, \
                  int64_t ntiles, int tile_rows) {                                              \
-    gather_vec_body<RB, U, NT>(jobs, ts, njobs, ntiles, tile_rows);                            \
+    gather_vec_body<RB, U, NT, GAS>(jobs, ts, njobs, ntiles, tile_rows);                       \
   }                                                                                            \
   struct NAME##_vgo {                                                                          \
     template <int RB, int U, bool NT>                                                          \
     static void go(const LaunchTable& t, hipStream_t s) {                                      \
-      hipLaunchKernelGGL((NAME##_vec<RB, U, NT>), dim3(t.grid), dim3(t.sched.block_threads),   \
-                         (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                     \
-                         t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows);    \
+      if (t.partial_win)                                                                       \
+        hipLaunchKernelGGL((NAME##_vec<RB, U, NT, false>), dim3(t.grid), dim3(t.sched.block_threads), \
+                           (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                   \
+                           t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows);  \
+      else                                                                                     \
+        hipLaunchKernelGGL((NAME##_vec<RB, U, NT, true>), dim3(t.grid), dim3(t.sched.block_threads), \
+                           (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                   \
+                           t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows);  \
     }                                                                                          \
   };                                                                                           \
   struct NAME##_go {                                                                           \

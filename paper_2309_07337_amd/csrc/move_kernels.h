@@ -44,13 +44,22 @@ template <> struct NumVec<float, 4> { using type = float; };
 template <> struct NumVec<double, 16> { using type = f64x2; };
 template <> struct NumVec<double, 8> { using type = double; };
 
-template <class T, bool NT>
-__device__ __forceinline__ T ldv(const T* p) {
+// Every buffer a job names is device (global) memory.  Pointers read from a
+// job table carry no address space, so the compiler would access them with
+// FLAT instructions (address-space checks, both wait counters, and LDS-window
+// reads merged into the same FLAT access); the bodies below cast them to the
+// global address space (HX_G), which gives global loads and stores with a
+// scalar base and 32-bit lane offsets, and keeps LDS reads as LDS reads.
+#define HX_G __attribute__((address_space(1)))
+#define HX_L __attribute__((address_space(3)))
+
+template <class T, bool NT, class P>
+__device__ __forceinline__ T ldv(P p) {
   if constexpr (NT) return __builtin_nontemporal_load(p);
   else return *p;
 }
-template <class T, bool NT>
-__device__ __forceinline__ void stv(T* p, T v) {
+template <class T, bool NT, class P>
+__device__ __forceinline__ void stv(P p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
@@ -119,9 +128,9 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
   int staged = -1;
   for (int64_t t = t0; t < t1; ++t) {
     while (t >= ts[j + 1]) ++j;
-    const char* __restrict__ src = jobs[j].src;
-    char* __restrict__ dst = jobs[j].dst;
-    const int32_t* __restrict__ idx = jobs[j].idx;
+    const HX_G char* __restrict__ src = (const HX_G char*)jobs[j].src;
+    HX_G char* __restrict__ dst = (HX_G char*)jobs[j].dst;
+    const HX_G int32_t* __restrict__ idx = (const HX_G int32_t*)jobs[j].idx;
     const int64_t nrows = jobs[j].nrows;
     const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
@@ -133,7 +142,7 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
         win_rows = jobs[j].win_rows;
         if (staged != j) {
           __syncthreads();  // every lane is done with the previous window
-          const V* __restrict__ wp = reinterpret_cast<const V*>(src + win_lo * (int64_t)rb);
+          const HX_G V* __restrict__ wp = reinterpret_cast<const HX_G V*>(src + win_lo * (int64_t)rb);
           const int nvec = (int)win_rows * NV;
           constexpr int UW = 8;  // loads in flight per lane while staging
           for (int i0 = threadIdx.x; i0 < nvec; i0 += blockDim.x * UW) {
@@ -159,8 +168,8 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
         // identity job: the tile is one contiguous byte range; copy it as a
         // flat stream of 16-byte vectors, 8 in flight per lane
         constexpr int UC = 8;
-        const V* __restrict__ sp = reinterpret_cast<const V*>(src + r0 * rb);
-        V* __restrict__ dp = reinterpret_cast<V*>(dst + r0 * rb);
+        const HX_G V* __restrict__ sp = reinterpret_cast<const HX_G V*>(src + r0 * rb);
+        HX_G V* __restrict__ dp = reinterpret_cast<HX_G V*>(dst + r0 * rb);
         const int64_t nvec = (r1 - r0) * NV;
         for (int64_t i = threadIdx.x; i < nvec; i += (int64_t)blockDim.x * UC) {
           V c[UC];
@@ -198,7 +207,7 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
           for (int u = 0; u < U; ++u) {
             const int64_t wr = srow[u] - win_lo;
             const bool inw = (uint64_t)wr < (uint64_t)win_rows;
-            const V* sp = reinterpret_cast<const V*>(src + srow[u] * rb);
+            const HX_G V* sp = reinterpret_cast<const HX_G V*>(src + srow[u] * rb);
 #pragma unroll
             for (int k = 0; k < NVPL; ++k) {
               const int vi = lane_v + k * LPR;
@@ -211,7 +220,7 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
         } else {
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const V* sp = reinterpret_cast<const V*>(src + srow[u] * rb);
+            const HX_G V* sp = reinterpret_cast<const HX_G V*>(src + srow[u] * rb);
 #pragma unroll
             for (int k = 0; k < NVPL; ++k) {
               const int vi = lane_v + k * LPR;
@@ -223,7 +232,7 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
         for (int u = 0; u < U; ++u) {
           const int64_t r = base + (int64_t)u * rows_per_pass;
           if (r < r1) {
-            V* dp = reinterpret_cast<V*>(dst + r * rb);
+            HX_G V* dp = reinterpret_cast<HX_G V*>(dst + r * rb);
 #pragma unroll
             for (int k = 0; k < NVPL; ++k) {
               const int vi = lane_v + k * LPR;
@@ -235,8 +244,8 @@ __device__ __forceinline__ void gather_body(const GatherJob* __restrict__ jobs, 
     } else {
       for (int64_t r = r0 + rsub; r < r1; r += rows_per_pass) {
         const int64_t s = idx ? (int64_t)ldv<int32_t, NT>(idx + r) : r;
-        const V* sp = reinterpret_cast<const V*>(src + s * rb);
-        V* dp = reinterpret_cast<V*>(dst + r * rb);
+        const HX_G V* sp = reinterpret_cast<const HX_G V*>(src + s * rb);
+        HX_G V* dp = reinterpret_cast<HX_G V*>(dst + r * rb);
         for (int vi = lane_v; vi < nv; vi += LPR) stv<V, NT>(dp + vi, sp[vi]);
       }
     }
@@ -270,12 +279,28 @@ __device__ __forceinline__ u32x4 pack16(const typename RawVec<RB>::type (&v)[16 
   else return u32x4{v[0], v[1], v[2], v[3]};
 }
 
-template <int RB, int U, bool NT>
+// A job's pointer as global memory (GAS) or without an address space.
+template <bool GAS, class T>
+__device__ __forceinline__ auto gas_ptr(T* p) {
+  if constexpr (GAS) return (HX_G T*)p;
+  else return p;
+}
+
+// GAS: the jobs' buffers are accessed as global memory (tables whose jobs
+// have no window, or whose indices all lie in it); otherwise without an
+// address space (FLAT), so that a row inside or outside the window is one
+// load of either address: measured faster on gfx950, for tables whose
+// windows miss some indices, than an LDS read plus a sparse global load.
+template <int RB, int U, bool NT, bool GAS>
 __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
                                                 int njobs, int64_t ntiles, int tile_rows) {
   constexpr int V = 16 / RB;
   using R = typename RawVec<RB>::type;
   using IV = typename IdxVec<RB>::type;
+  using RP = decltype(gas_ptr<GAS>((R*)nullptr));
+  using CRP = decltype(gas_ptr<GAS>((const R*)nullptr));
+  using CIVP = decltype(gas_ptr<GAS>((const IV*)nullptr));
+  using VP = decltype(gas_ptr<GAS>((u32x4*)nullptr));
   extern __shared__ __align__(16) unsigned char s_dyn[];
   int64_t t0, t1;
   tile_range(ntiles, &t0, &t1);
@@ -286,9 +311,9 @@ __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jo
   const int bd = blockDim.x, tid = threadIdx.x;
   for (int64_t t = t0; t < t1; ++t) {
     while (t >= ts[j + 1]) ++j;
-    const char* __restrict__ src = jobs[j].src;
-    char* __restrict__ dst = jobs[j].dst;
-    const int32_t* __restrict__ idx = jobs[j].idx;
+    const auto src = gas_ptr<GAS>(jobs[j].src);
+    const auto dst = gas_ptr<GAS>(jobs[j].dst);
+    const auto idx = gas_ptr<GAS>(jobs[j].idx);
     const int64_t nrows = jobs[j].nrows;
     const int32_t win_lo = (int32_t)jobs[j].win_lo;
     const uint32_t win_rows = (uint32_t)jobs[j].win_rows;
@@ -309,8 +334,12 @@ __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jo
     // a row's value: from the staged window when it lies there, else global memory
     auto read_row = [&](int32_t sr) -> R {
       const uint32_t w = (uint32_t)(sr - win_lo);
-      if (use_win && w < win_rows) return *reinterpret_cast<const R*>(s_dyn + lds_a + w * (uint32_t)RB);
-      return *reinterpret_cast<const R*>(src + (int64_t)sr * RB);
+      if constexpr (GAS) {
+        if (use_win && w < win_rows) return *(const HX_L R*)(s_dyn + lds_a + w * (uint32_t)RB);
+      } else {
+        if (use_win && w < win_rows) return *reinterpret_cast<const R*>(s_dyn + lds_a + w * (uint32_t)RB);
+      }
+      return *reinterpret_cast<CRP>(src + (int64_t)sr * RB);
     };
     // the U index vectors of a lane for the pass starting at group g0
     // (lanes past the last group reload it: valid loads; stores are predicated)
@@ -319,7 +348,7 @@ __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jo
       for (int u = 0; u < U; ++u) {
         const int64_t g = min(g0 + tid + (int64_t)u * bd, max(ng - 1, (int64_t)0));
         if (idx) {
-          iv[u] = ldv<IV, NT>(reinterpret_cast<const IV*>(idx + a) + g);
+          iv[u] = ldv<IV, NT>(reinterpret_cast<CIVP>(idx + a) + g);
         } else {
 #pragma unroll
           for (int k = 0; k < V; ++k) iv[u][k] = (int)(a + g * V + k);
@@ -335,7 +364,7 @@ __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jo
         const uintptr_t base = A & ~(uintptr_t)15;
         const uintptr_t A16 = (A + 15) & ~(uintptr_t)15, B16 = B & ~(uintptr_t)15;
         const int nv = B16 > A16 ? (int)((B16 - A16) >> 4) : 0;
-        const u32x4* __restrict__ gp = reinterpret_cast<const u32x4*>(A16);
+        const auto gp = gas_ptr<GAS>(reinterpret_cast<const u32x4*>(A16));
         u32x4* sp = reinterpret_cast<u32x4*>(s_dyn + (A16 - base));
         // all of a lane's staging loads in flight together (an 80 KiB window
         // is at most 10 per lane with 512 lanes)
@@ -353,14 +382,16 @@ __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jo
         if (tid < 8) {
           const uintptr_t w = tid < 4 ? A + 4 * (uintptr_t)tid : max(B16, A16) + 4 * (uintptr_t)(tid - 4);
           const bool ok = tid < 4 ? (w < A16 && w < B) : (w < B);
-          if (ok) *reinterpret_cast<unsigned int*>(s_dyn + (w - base)) = *reinterpret_cast<const unsigned int*>(w);
+          if (ok)
+            *reinterpret_cast<unsigned int*>(s_dyn + (w - base)) =
+                *gas_ptr<GAS>(reinterpret_cast<const unsigned int*>(w));
         }
         lds_a = (uint32_t)(A - base);
         staged = j;
       }
       __syncthreads();  // the window is visible to every lane
     }
-    if (ng == 0 && has_edge) stv<R, NT>(reinterpret_cast<R*>(dst + er * RB), read_row(esr));
+    if (ng == 0 && has_edge) stv<R, NT>(reinterpret_cast<RP>(dst + er * RB), read_row(esr));
     // passes of U groups per lane (a tile is usually one pass); the next
     // pass's indices are loaded while this pass's rows are read and stored,
     // and the lane's row outside the groups goes with the first pass
@@ -377,9 +408,9 @@ __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jo
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t g = g0 + tid + (int64_t)u * bd;
-        if (g < ng) stv<u32x4, NT>(reinterpret_cast<u32x4*>(dst + a * RB) + g, pack16<RB>(v[u]));
+        if (g < ng) stv<u32x4, NT>(reinterpret_cast<VP>(dst + a * RB) + g, pack16<RB>(v[u]));
       }
-      if (g0 == 0 && has_edge) stv<R, NT>(reinterpret_cast<R*>(dst + er * RB), ev);
+      if (g0 == 0 && has_edge) stv<R, NT>(reinterpret_cast<RP>(dst + er * RB), ev);
     }
     signal_tile(jobs[j].ready, r1 - r0);
   }
@@ -417,10 +448,10 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
   int j = find_job(ts, njobs, t0);
   for (int64_t t = t0; t < t1; ++t) {
     while (t >= ts[j + 1]) ++j;
-    const char* __restrict__ in = jobs[j].in;
-    char* __restrict__ out = jobs[j].out;
-    const int32_t* __restrict__ ptr = jobs[j].ptr;
-    const int32_t* __restrict__ idx = jobs[j].idx;
+    const HX_G char* __restrict__ in = (const HX_G char*)jobs[j].in;
+    HX_G char* __restrict__ out = (HX_G char*)jobs[j].out;
+    const HX_G int32_t* __restrict__ ptr = (const HX_G int32_t*)jobs[j].ptr;
+    const HX_G int32_t* __restrict__ idx = (const HX_G int32_t*)jobs[j].idx;
     const int64_t nrows = jobs[j].nrows;
     const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
@@ -465,7 +496,7 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
           for (int u = 0; u < U; ++u) {
             const int e = min(base + u * rows_per_pass, ne - 1);
             dsl[u] = s_idx[e];
-            const V* sp = reinterpret_cast<const V*>(in + (r0 + s_row[e]) * (int64_t)rb);
+            const HX_G V* sp = reinterpret_cast<const HX_G V*>(in + (r0 + s_row[e]) * (int64_t)rb);
 #pragma unroll
             for (int k = 0; k < NVPL; ++k) {
               const int vi = lane_v + k * LPR;
@@ -475,7 +506,7 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             if (base + u * rows_per_pass < ne) {
-              V* dp = reinterpret_cast<V*>(out + (int64_t)dsl[u] * rb);
+              HX_G V* dp = reinterpret_cast<HX_G V*>(out + (int64_t)dsl[u] * rb);
 #pragma unroll
               for (int k = 0; k < NVPL; ++k) {
                 const int vi = lane_v + k * LPR;
@@ -510,7 +541,7 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (len[u] > 0) {
-            const V* sp = reinterpret_cast<const V*>(in + (base + (int64_t)u * rows_per_pass) * rb);
+            const HX_G V* sp = reinterpret_cast<const HX_G V*>(in + (base + (int64_t)u * rows_per_pass) * rb);
 #pragma unroll
             for (int k = 0; k < NVPL; ++k) {
               const int vi = lane_v + k * LPR;
@@ -523,7 +554,7 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
           for (int u = 0; u < U; ++u) {
             if (d < len[u]) {
               const int32_t dst = ldv<int32_t, NT>(idx + a[u] + d);
-              V* dp = reinterpret_cast<V*>(out + (int64_t)dst * rb);
+              HX_G V* dp = reinterpret_cast<HX_G V*>(out + (int64_t)dst * rb);
 #pragma unroll
               for (int k = 0; k < NVPL; ++k) {
                 const int vi = lane_v + k * LPR;
@@ -537,12 +568,12 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
     } else {
       for (int64_t r = r0 + rsub; r < r1; r += rows_per_pass) {
         const int32_t p0 = ptr[r], p1 = ptr[r + 1];
-        const V* sp = reinterpret_cast<const V*>(in + r * rb);
+        const HX_G V* sp = reinterpret_cast<const HX_G V*>(in + r * rb);
         for (int vi = lane_v; vi < nv; vi += LPR) {
           if (p0 >= p1) break;
           const V v = sp[vi];
           for (int32_t e = p0; e < p1; ++e)
-            stv<V, NT>(reinterpret_cast<V*>(out + (int64_t)idx[e] * rb) + vi, v);
+            stv<V, NT>(reinterpret_cast<HX_G V*>(out + (int64_t)idx[e] * rb) + vi, v);
         }
       }
     }
@@ -565,7 +596,8 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
 
 // Address of term t of a segmented sum: row t of the first input, or row
 // t - split of the second one.
-__device__ __forceinline__ const char* term_row(const char* in, const char* in2, int32_t split, int32_t t, size_t rb) {
+template <class CP>
+__device__ __forceinline__ CP term_row(CP in, CP in2, int32_t split, int32_t t, size_t rb) {
   return t < split ? in + (int64_t)t * (int64_t)rb : in2 + (int64_t)(t - split) * (int64_t)rb;
 }
 
@@ -588,6 +620,8 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
   // without a term buffer the tile runs row-parallel straight from global
   // memory (no staging, no barriers)
   const bool stage_ptr = NV > 0 && tile_rows <= STAGE_ROWS && cap_terms > 0;
+  // (job pointers are accessed without an address space here: FLAT loads
+  // measured faster than global ones for this body on gfx950)
   int64_t t0, t1;
   tile_range(ntiles, &t0, &t1);
   if (t0 >= t1) return;
@@ -804,12 +838,12 @@ __device__ __forceinline__ void segsum_win_body(const SegSumJob* __restrict__ jo
   int staged = -1;
   for (int64_t t = t0; t < t1; ++t) {
     while (t >= ts[j + 1]) ++j;
-    const char* __restrict__ in = jobs[j].in;
+    const HX_G char* __restrict__ in = (const HX_G char*)jobs[j].in;
     const int32_t split = jobs[j].split;
-    const char* __restrict__ in2 = jobs[j].in2;
-    char* __restrict__ out = jobs[j].out;
-    const int32_t* __restrict__ ptr = jobs[j].ptr;
-    const int32_t* __restrict__ idx = jobs[j].idx;
+    const HX_G char* __restrict__ in2 = (const HX_G char*)jobs[j].in2;
+    HX_G char* __restrict__ out = (HX_G char*)jobs[j].out;
+    const HX_G int32_t* __restrict__ ptr = (const HX_G int32_t*)jobs[j].ptr;
+    const HX_G int32_t* __restrict__ idx = (const HX_G int32_t*)jobs[j].idx;
     const int64_t nrows = jobs[j].nrows;
     const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
@@ -817,7 +851,7 @@ __device__ __forceinline__ void segsum_win_body(const SegSumJob* __restrict__ jo
     const int32_t win_rows = (int32_t)jobs[j].win_rows;
     if (win_rows > 0 && staged != j) {
       __syncthreads();  // every lane is done with the previous window
-      const V* __restrict__ wp = reinterpret_cast<const V*>(term_row(in, in2, split, win_lo, rb));
+      const HX_G V* __restrict__ wp = reinterpret_cast<const HX_G V*>(term_row(in, in2, split, win_lo, rb));
       const int nvec = win_rows * NV;
       constexpr int UW = 8;
       for (int i0 = threadIdx.x; i0 < nvec; i0 += blockDim.x * UW) {
@@ -867,12 +901,12 @@ __device__ __forceinline__ void segsum_win_body(const SegSumJob* __restrict__ jo
             if (NV % LPR == 0 || vi < NV) {
               V v;
               if (wr < (uint32_t)win_rows) v = s_win[(int64_t)wr * NV + vi];
-              else v = reinterpret_cast<const V*>(term_row(in, in2, split, tm, rb))[vi];
+              else v = reinterpret_cast<const HX_G V*>(term_row(in, in2, split, tm, rb))[vi];
               acc[k] = d == 0 ? v : acc[k] + v;
             }
           }
         }
-        V* dp = reinterpret_cast<V*>(out + r * (int64_t)rb);
+        HX_G V* dp = reinterpret_cast<HX_G V*>(out + r * (int64_t)rb);
 #pragma unroll
         for (int k = 0; k < NVPL; ++k) {
           const int vi = lane_v + k * LPR;
@@ -881,6 +915,157 @@ __device__ __forceinline__ void segsum_win_body(const SegSumJob* __restrict__ jo
       }
     }
     __syncthreads();  // the next tile overwrites the staged pointers and indices
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order segmented sum of short rows (one FP32 or FP64 value per row),
+// one row per lane: a pass gives each lane U rows, lane-strided, so that the
+// rows' pointer loads, their entries' loads and the stores are coalesced
+// across the wavefront.  The passes are pipelined: row pointers two passes
+// ahead, the entries of every row's first D terms one pass ahead (all
+// together; deeper terms one after another), this pass's values issued before
+// those prefetches; a term inside the job's LDS window
+// (terms [win_lo, win_lo + win_rows), all in one input, staged once per job
+// with every load in flight at once) is read from LDS, any other from global
+// memory.  Per row the adds run in entry order from the first term (a lone
+// -0 stays -0); an empty row stores +0.
+// ---------------------------------------------------------------------------
+template <class T, int U, int D, bool NT>
+__device__ __forceinline__ void segsum_vec_body(const SegSumJob* __restrict__ jobs, const int64_t* __restrict__ ts,
+                                                int njobs, int64_t ntiles, int tile_rows) {
+  constexpr int RB = (int)sizeof(T);
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  int64_t t0, t1;
+  tile_range(ntiles, &t0, &t1);
+  if (t0 >= t1) return;
+  int j = find_job(ts, njobs, t0);
+  int staged = -1;
+  uint32_t lds_a = 0;  // LDS byte of the staged window's first term (0..15)
+  const int bd = blockDim.x, tid = threadIdx.x;
+  const int64_t step = (int64_t)bd * U;  // rows per pass
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= ts[j + 1]) ++j;
+    const HX_G char* __restrict__ in = (const HX_G char*)jobs[j].in;
+    const HX_G char* __restrict__ in2 = (const HX_G char*)jobs[j].in2;
+    const int32_t split = jobs[j].split;
+    HX_G char* __restrict__ out = (HX_G char*)jobs[j].out;
+    const HX_G int32_t* __restrict__ ptr = (const HX_G int32_t*)jobs[j].ptr;
+    const HX_G int32_t* __restrict__ idx = (const HX_G int32_t*)jobs[j].idx;
+    const int64_t nrows = jobs[j].nrows;
+    const int32_t win_lo = (int32_t)jobs[j].win_lo;
+    const uint32_t win_rows = (uint32_t)jobs[j].win_rows;
+    const int64_t r0 = (t - ts[j]) * (int64_t)tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, nrows);
+    const bool use_win = win_rows > 0;
+    auto term = [&](int32_t tm) -> T {
+      const uint32_t w = (uint32_t)(tm - win_lo);
+      if (use_win && w < win_rows) return *(const HX_L T*)(s_dyn + lds_a + w * (uint32_t)RB);
+      return *reinterpret_cast<const HX_G T*>(term_row(in, in2, split, tm, RB));
+    };
+    // row pointers of a lane's U rows of the pass starting at row base
+    // (lanes past the tile's end reload its last row: valid loads)
+    auto load_ptr = [&](int64_t base, int32_t (&xa)[U], int32_t (&xl)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = min(base + tid + (int64_t)u * bd, r1 - 1);
+        xa[u] = ptr[r];
+        xl[u] = ptr[r + 1];
+      }
+    };
+    // entries of the first D terms of those rows (xl: row lengths)
+    auto load_idx = [&](const int32_t (&xa)[U], const int32_t (&xl)[U], int32_t (&xe)[U][D]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int d = 0; d < D; ++d) xe[u][d] = xl[u] > d ? ldv<int32_t, NT>(idx + xa[u] + d) : 0;
+    };
+    auto lengths = [&](int32_t (&xa)[U], int32_t (&xl)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) xl[u] -= xa[u];
+    };
+    // pipeline: pointers two passes ahead, entries one pass ahead
+    int32_t a[U], len[U], an[U], ln[U];
+    int32_t e[U][D];
+    load_ptr(r0, a, len);
+    if (r0 + step < r1) load_ptr(r0 + step, an, ln);
+    if (use_win) {
+      if (staged != j) {
+        if (staged >= 0) __syncthreads();  // every lane is done with the previous window
+        const uintptr_t A = (uintptr_t)term_row(in, in2, split, win_lo, RB), B = A + (uintptr_t)win_rows * RB;
+        const uintptr_t base = A & ~(uintptr_t)15;
+        const uintptr_t A16 = (A + 15) & ~(uintptr_t)15, B16 = B & ~(uintptr_t)15;
+        const int nv = B16 > A16 ? (int)((B16 - A16) >> 4) : 0;
+        const HX_G u32x4* __restrict__ gp = reinterpret_cast<const HX_G u32x4*>(A16);
+        u32x4* sp = reinterpret_cast<u32x4*>(s_dyn + (A16 - base));
+        constexpr int UW = 10;  // all of a lane's staging loads in flight together (80 KiB, 512 lanes)
+        for (int i0 = tid; i0 < nv; i0 += bd * UW) {
+          u32x4 w[UW];
+#pragma unroll
+          for (int u = 0; u < UW; ++u)
+            if (i0 + u * bd < nv) w[u] = gp[i0 + u * bd];
+#pragma unroll
+          for (int u = 0; u < UW; ++u)
+            if (i0 + u * bd < nv) sp[i0 + u * bd] = w[u];
+        }
+        // ragged ends: 4-byte words in [A, min(A16, B)) and [max(B16, A16), B)
+        if (tid < 8) {
+          const uintptr_t w = tid < 4 ? A + 4 * (uintptr_t)tid : max(B16, A16) + 4 * (uintptr_t)(tid - 4);
+          const bool ok = tid < 4 ? (w < A16 && w < B) : (w < B);
+          if (ok) *reinterpret_cast<unsigned int*>(s_dyn + (w - base)) = *reinterpret_cast<const HX_G unsigned int*>(w);
+        }
+        lds_a = (uint32_t)(A - base);
+        staged = j;
+      }
+      __syncthreads();  // the window is visible to every lane
+    }
+    lengths(a, len);
+    load_idx(a, len, e);
+    for (int64_t base = r0; base < r1; base += step) {
+      // this pass's values first, then the next passes' prefetches (so that
+      // waiting for the values never waits for the prefetches)
+      T v[U][D];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[u][d] = len[u] > d ? term(e[u][d]) : (T)0;
+      __builtin_amdgcn_sched_barrier(0);
+      const bool more = base + step < r1;
+      int32_t a1[U], l1[U], e1[U][D];
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          a1[u] = an[u];
+          l1[u] = ln[u] - an[u];
+        }
+        load_idx(a1, l1, e1);
+        if (base + 2 * step < r1) load_ptr(base + 2 * step, an, ln);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      T acc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        acc[u] = v[u][0];
+#pragma unroll
+        for (int d = 1; d < D; ++d)
+          if (len[u] > d) acc[u] = acc[u] + v[u][d];
+        for (int32_t d = D; d < len[u]; ++d) acc[u] = acc[u] + term(ldv<int32_t, NT>(idx + a[u] + d));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = base + tid + (int64_t)u * bd;
+        if (r < r1) stv<T, NT>(reinterpret_cast<HX_G T*>(out + r * RB), acc[u]);
+      }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          a[u] = a1[u];
+          len[u] = l1[u];
+#pragma unroll
+          for (int d = 0; d < D; ++d) e[u][d] = e1[u][d];
+        }
+      }
+    }
   }
 }
 

@@ -773,6 +773,7 @@ static bool batch_has_ready(const hx_batch* b) {
 
 int hx::batch_init_scheds(hx_batch* b, const hx_sched* sched) {
   for (int ph = 0; ph < 4; ++ph) {
+    b->sched_from_cache[ph] = sched == nullptr;
     const int kind = ph == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
     if (sched) {
       b->sched[ph] = resolve_sched(sched, kind, (int)b->row_bytes);
@@ -831,6 +832,7 @@ extern "C" int hx_batch_set_sched(hx_batch* b, int phase, const hx_sched* sched)
   const int kind = phase == PH_BWD ? KIND_SEGSUM : KIND_GATHER;
   const Sched old = b->sched[phase];
   b->sched[phase] = resolve_sched(sched, kind, (int)b->row_bytes);
+  b->sched_from_cache[phase] = false;
   if (phase == PH_PACK && batch_has_ready(b)) b->sched[PH_PACK].push_pack = 0;
   const int rc = batch_prepare(b);
   if (rc != HX_SUCCESS) {
@@ -943,6 +945,9 @@ extern "C" int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out) {
                                         b->E1_tot}};
     HX_TRY(build_gather_table(x1, b->dtype, rbi, gsc, &b->lt_xfer[2]));
   }
+  // the backward's shape (and so its tuning-cache key) exists only now
+  Sched cached;
+  if (b->sched_from_cache[PH_BWD] && cache_lookup(cache_key(b, PH_BWD), &cached)) b->sched[PH_BWD] = cached;
   return batch_prepare(b);
 }
 
@@ -970,6 +975,8 @@ static int run_backward(hx_batch* b, hipStream_t s, bool plain_form) {
 static int refresh_member_grads(hx_batch* b) {
   if (b->world || member_grad_gens(b) == b->bwd_gens_captured) return HX_SUCCESS;
   b->plain_built[PH_BWD] = false;
+  Sched cached;  // gradients bound after the batch was made: the backward's cache key changes
+  if (b->sched_from_cache[PH_BWD] && cache_lookup(cache_key(b, PH_BWD), &cached)) b->sched[PH_BWD] = cached;
   return batch_prepare(b);
 }
 
@@ -1108,6 +1115,24 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
             consider(c);
           }
     }
+    // seeds for segmented sums of rows of one value: one row per lane,
+    // per-job LDS term windows or none, one-shot grids
+    if (ph == PH_BWD && (rb == 4 || rb == 8) && (size_t)rb == dtype_bytes(b->dtype)) {
+      for (int win : {1, 0})
+        for (int bt : {256, 512})
+          for (int u : {2, 4}) {
+            Sched c = best;
+            c.pair_rows = 1;
+            c.lds_window = win;
+            c.tile_rows = 16384;
+            c.block_threads = bt;
+            c.blocks_per_cu = kOneShotBpc;
+            c.unroll = u;
+            c.nontemporal = 0;
+            c.per_neighbor = 0;
+            consider(c);
+          }
+    }
     // stage 1: work per tile, rows in flight, pull vs push (pack), LDS
     // source windows and two rows per lane (gathers); stage 2: launch shape
     // (persistent or one-shot grid, workgroup size) and streaming hints;
@@ -1122,8 +1147,11 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
               for (int pair : {0, 1}) {
                 if (push && (ph != PH_PACK || batch_has_ready(b))) continue;
                 if (win && push) continue;
-                // 16-byte row groups per lane: pull gathers of 4- or 8-byte rows
-                if (pair && ((b->row_bytes != 8 && b->row_bytes != 4) || push || ph == PH_BWD)) continue;
+                // 16-byte row groups per lane: pull gathers of 4- or 8-byte rows;
+                // segmented sums of rows of one value: one row per lane
+                if (pair && ((b->row_bytes != 8 && b->row_bytes != 4) || push ||
+                             (ph == PH_BWD && b->row_bytes != dtype_bytes(b->dtype))))
+                  continue;
                 Sched c = s0;
                 c.tile_rows = std::max(16, base * tf / 8);
                 c.unroll = u;
@@ -1177,6 +1205,7 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     }
     if (rc == HX_SUCCESS) {
       b->sched[ph] = best;
+      b->sched_from_cache[ph] = false;  // tuned here: kept when gradients are bound again
       cache_store(cache_key(b, ph), best);
     }
   }
