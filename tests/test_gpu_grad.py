@@ -62,16 +62,21 @@ def test_backward_grid3d_64_columns():
     assert bits_equal(host(x.grad), OM.exchange_adjoint_reference(halos, gy, n))
 
 
-def test_backward_random_rows_sampled_rows():
-    """Full size (4096 ranks, 64 FP32 columns): rows sampled from every
-    fan-out class are recomputed one by one by the oracle's definition."""
+def test_backward_random_rows_every_row():
+    """Full size (4096 ranks, 64 FP32 columns, the differentiation workload):
+    every row of the backward, in 16-column chunks, against the closed-form
+    adjoint in ascending rank order (the pinned OpenMP loops of
+    oracle/cpu_move.c over the adjoint CSR), and every halo row of the
+    forward against the direct gather."""
     need_gpu()
     import torch
+    from oracle import cpu as OC
+    OC.build_cpu()
     rs, rp, cols = cached_random_rows()
     halos = OP.all_halos(rp, cols, rs)
     n = int(rs[-1])
     C = 64
-    say("grad random_rows")
+    say("grad random_rows, every row")
     ex, _ = exchange_for(rs, rp, cols, 128, "plain", C)
     H = ex.halo.shape[0]
     ex.x.copy_(dev(uniform_pm1_f32(5, n * C).reshape(n, C)))
@@ -85,24 +90,20 @@ def test_backward_random_rows_sampled_rows():
     gx = ex.backward()
     torch.cuda.synchronize()
     allcols = np.concatenate(halos)
-    order = np.argsort(allcols, kind="stable")
-    counts = np.bincount(allcols, minlength=n)
-    ptr = np.concatenate([[0], np.cumsum(counts)])
-    rng = np.random.default_rng(0)
-    sample = []
-    for f in np.unique(counts):
-        rows = np.nonzero(counts == f)[0]
-        sample += rng.choice(rows, size=min(8, rows.size), replace=False).tolist()
-    gx_s = host(gx[torch.as_tensor(sample, device="cuda")])
-    for i, c in enumerate(sample):
-        pos = order[ptr[c]:ptr[c + 1]]
-        vals = host(g[torch.as_tensor(pos, device="cuda")]) if pos.size else np.zeros((0, C), np.float32)
-        want = OM.segmented_sum_fixed_order(vals, np.array([0, pos.size]), np.arange(pos.size))[0]
-        assert bits_equal(gx_s[i], want), (c, counts[c])
-    # forward at full size: sampled halo rows against the direct gather
-    idx = rng.choice(H, size=4096, replace=False)
+    # adjoint CSR: column -> halo entries holding it, ascending (= ascending rank)
+    perm = np.argsort(allcols, kind="stable").astype(np.int32)
+    ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(allcols, minlength=n), out=ptr[1:])
+    ptr = ptr.astype(np.int32)
+    for c0 in range(0, C, 16):
+        vals = np.ascontiguousarray(host(g[:, c0:c0 + 16]))
+        want = OC.transpose_sum(vals, ptr, perm)
+        assert bits_equal(np.ascontiguousarray(host(gx[:, c0:c0 + 16])), want), c0
+        del vals, want
     xs = host(ex.x)
-    assert bits_equal(host(y[torch.as_tensor(idx, device="cuda")]), xs[allcols[idx]])
+    for lo in range(0, H, step):
+        hi = min(H, lo + step)
+        assert bits_equal(host(y[lo:hi]), xs[allcols[lo:hi]]), lo
 
 
 def test_finite_differences():
@@ -330,3 +331,92 @@ def test_staged_backward_random_rows_exact_values():
     for c in rows:
         lo, hi = np.searchsorted(sh, c), np.searchsorted(sh, c, side="right")
         assert got[c] == float(np.sum(gh[order[lo:hi]]))
+
+
+def test_staged_backward_random_rows_fp32_by_definition():
+    """2^22 x 32, 4096 ranks, 2-step locality plan, one FP32 value per row:
+    the staged backward at full size (with the simulated reverse transfers),
+    every owned row of a dozen ranks recomputed from the stages' definition
+    (reading R15) by walking the plan's lists: each stage-1 send slot of the
+    row, ascending, contributes its receiver's stage-1 receive-slot sum, which
+    is the receiver's own halo term (if its halo reads the slot) followed by
+    the gradients of the redistribution entries forwarding that slot, in
+    ascending entry, each being the gradient of the halo entry its destination
+    unpacks it into; all additions sequential in FP32."""
+    need_gpu()
+    import torch
+    from paper_2309_07337_amd.autograd import HaloExchange
+    rs, rp, cols = cached_random_rows()
+    say("staged backward random_rows by definition")
+    plan = gpu_plan(rs, rp, cols, 128, "locality")
+    R, n = len(rs) - 1, int(rs[-1])
+    hsz = np.array([P.hx_plan_field(plan, r, "halo").size for r in range(R)], np.int64)
+    hoff = np.concatenate([[0], np.cumsum(hsz)])
+    H = int(hoff[-1])
+    ex = HaloExchange(plan, n, H, 1, dtype=torch.float32, staged_backward=True)
+    gh = uniform_pm1_f32(9, H)
+    ex.g_halo.copy_(dev(gh.reshape(H, 1)))
+    P.hx_batch_backward(ex.batch)
+    got = host(ex.g_x)[:, 0]
+    cache = {}
+
+    def F(r, name):
+        key = (r, name)
+        if key not in cache:
+            cache[key] = P.hx_plan_field(plan, r, name).astype(np.int64)
+        return cache[key]
+
+    def inv_unpack(t):
+        key = (t, "inv")
+        if key not in cache:
+            us = F(t, "unpack_src")
+            nslots = int(F(t, "r1_counts").sum() + F(t, "r2_counts").sum())
+            inv = np.full(nslots, -1, np.int64)
+            inv[us] = np.arange(us.size)
+            cache[key] = inv
+        return cache[key]
+
+    def seq_sum(vals):
+        acc = np.float32(vals[0])
+        for v in vals[1:]:
+            acc = np.float32(acc + np.float32(v))
+        return acc
+
+    def recv1_slot_sum(t, q):
+        terms = []
+        own = inv_unpack(t)[q]
+        if own >= 0:
+            terms.append(gh[hoff[t] + own])
+        s2src, s2d, s2p = F(t, "s2_src"), F(t, "s2_displs"), F(t, "s2_procs")
+        for e in np.nonzero(s2src == q)[0]:
+            m2 = int(np.searchsorted(s2d, e, side="right") - 1)
+            d = int(s2p[m2])
+            pos = int(np.nonzero(F(d, "r2_procs") == t)[0][0])
+            slot = int(F(d, "r1_counts").sum()) + int(F(d, "r2_displs")[pos]) + int(e - s2d[m2])
+            j = inv_unpack(d)[slot]
+            assert j >= 0
+            terms.append(gh[hoff[d] + j])
+        assert terms, (t, q)
+        return seq_sum(terms)
+
+    checked = 0
+    for r in (0, 1, 1511, 2048, 2300, 4095, 777, 3001, 127, 128, 3968, 1023):
+        s1i, s1d, s1p = F(r, "s1_idx"), F(r, "s1_displs"), F(r, "s1_procs")
+        order = np.argsort(s1i, kind="stable")
+        bounds = np.searchsorted(s1i[order], np.arange(int(rs[r + 1] - rs[r]) + 1))
+        for lc in range(int(rs[r + 1] - rs[r])):
+            slots = order[bounds[lc]:bounds[lc + 1]]      # ascending slot
+            if slots.size == 0:
+                want = np.float32(0.0)
+            else:
+                parts = []
+                for k in slots:
+                    m = int(np.searchsorted(s1d, k, side="right") - 1)
+                    t = int(s1p[m])
+                    pos = int(np.nonzero(F(t, "r1_procs") == r)[0][0])
+                    parts.append(recv1_slot_sum(t, int(F(t, "r1_displs")[pos]) + int(k - s1d[m])))
+                want = seq_sum(parts)
+            c = int(rs[r]) + lc
+            assert got[c].view(np.uint32) == np.float32(want).view(np.uint32), (r, lc, slots.size)
+            checked += 1
+    say("  rows checked:", checked)
