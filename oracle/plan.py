@@ -20,15 +20,20 @@ Source passages (MPI Advance, Bienz, Schafer, Skjellum, 2023):
 Readings of what the paper leaves open:
 
 * R1  contiguous ownership: rank p owns rows/columns [row_starts[p], row_starts[p+1]).
-* R2  block placement: node(p) = p // ppn, lrank(p) = p % ppn; the last node
-      may hold fewer ranks, cnt(m) = min(ppn, R - m*ppn).
+* R2  placement of R ranks on NN = ceil(R / ppn) nodes, block (the default):
+      node(p) = p // ppn, lrank(p) = p % ppn, the last node may hold fewer
+      ranks, cnt(m) = min(ppn, R - m*ppn); or cyclic (round robin):
+      node(p) = p mod NN, lrank(p) = p // NN, cnt(m) = (R - 1 - m) // NN + 1.
+      The rank of node m with local rank l is m*ppn + l (block) or l*NN + m
+      (cyclic); a node's ranks are listed in ascending rank order.
 * R3  orders: neighbor lists ascending by rank; entries of one message
       ascending by global index; displacements are exclusive prefix sums;
       empty messages are omitted; a rank never messages itself.  The halo is
       ordered by ascending global column, which equals the plain receive order.
 * R4  locality-aware variant = "2-step": rank q sends the deduplicated union
       D(q -> m) of what node m needs from it to its partner
-      partner(q, m) = m*ppn + (lrank(q) mod cnt(m)) on each remote node m; on-node
+      partner(q, m) = the rank of node m with local rank lrank(q) mod cnt(m)
+      (block: m*ppn + (lrank(q) mod cnt(m))) on each remote node m; on-node
       neighbors are served directly, as in the plain variant; the partner then
       forwards to every other rank of its node the entries of that rank's halo
       it received (redistribution), ordered by destination, then source rank,
@@ -88,35 +93,47 @@ def transpose_csr(send_idx, n_local: int):
 
 
 class Decomposition:
-    """All ranks' halos plus the ownership/placement conventions R1-R4."""
+    """All ranks' halos plus the ownership/placement conventions R1-R4.
 
-    def __init__(self, halos, row_starts, ppn: int):
+    ``placement``: "block" or "cyclic" rank-to-node placement (R2)."""
+
+    def __init__(self, halos, row_starts, ppn: int, placement: str = "block"):
         self.halos = [np.asarray(h, np.int64) for h in halos]
         self.row_starts = np.asarray(row_starts, np.int64)
         self.R = len(self.row_starts) - 1
         self.ppn = int(ppn)
         if self.ppn < 1:
             raise ValueError("ppn must be >= 1")
+        if placement not in ("block", "cyclic"):
+            raise ValueError(placement)
+        self.placement = placement
 
     # --- placement (R2) ---------------------------------------------------
-    def node(self, p: int) -> int:
-        return p // self.ppn
-
-    def lrank(self, p: int) -> int:
-        return p % self.ppn
-
     def nnodes(self) -> int:
         return (self.R + self.ppn - 1) // self.ppn
 
+    def node(self, p: int) -> int:
+        return p % self.nnodes() if self.placement == "cyclic" else p // self.ppn
+
+    def lrank(self, p: int) -> int:
+        return p // self.nnodes() if self.placement == "cyclic" else p % self.ppn
+
     def cnt(self, m: int) -> int:
+        if self.placement == "cyclic":
+            return (self.R - 1 - m) // self.nnodes() + 1
         return min(self.ppn, self.R - m * self.ppn)
 
-    def node_ranks(self, m: int) -> range:
-        return range(m * self.ppn, m * self.ppn + self.cnt(m))
+    def rank_at(self, m: int, l: int) -> int:
+        """The rank of node m with local rank l."""
+        return l * self.nnodes() + m if self.placement == "cyclic" else m * self.ppn + l
+
+    def node_ranks(self, m: int) -> list:
+        """Ranks of node m, ascending."""
+        return sorted(self.rank_at(m, l) for l in range(self.cnt(m)))
 
     def partner(self, q: int, m: int) -> int:
         """Rank of node m that receives q's aggregated message (reading R4)."""
-        return m * self.ppn + (self.lrank(q) % self.cnt(m))
+        return self.rank_at(m, self.lrank(q) % self.cnt(m))
 
     def n_local(self, p: int) -> int:
         return int(self.row_starts[p + 1] - self.row_starts[p])
@@ -284,7 +301,10 @@ class Decomposition:
                     bt_ptr=bt_ptr, bt_perm=bt_perm)
 
     # --- locality-aware 3-step variant (Sec. 2.2, aggregation; reading R16) -
+    # (block placement only: an aggregator packs its node's contiguous rows)
     def node_start(self, n: int) -> int:
+        if self.placement != "block":
+            raise ValueError("the 3-step variant needs block placement (a node's rows contiguous)")
         return int(self.row_starts[n * self.ppn])
 
     def node_rows(self, n: int) -> int:

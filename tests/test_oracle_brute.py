@@ -42,11 +42,33 @@ def brute_halo(row_starts, row_ptr, cols, r):
     return sorted(s)
 
 
-def build(case):
+def build(case, placement="block"):
     n, R, mx, pf, seed, uneven, ppn = case
     rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
     halos = P.all_halos(rp, cols, rs)
-    return rs, rp, cols, halos, P.Decomposition(halos, rs, ppn)
+    return rs, rp, cols, halos, P.Decomposition(halos, rs, ppn, placement)
+
+
+def placement_fns(R, ppn, placement):
+    """Node of a rank, the ranks of a node (ascending) and a rank's partner
+    on a node, written out independently of the oracle (reading R2)."""
+    NN = (R + ppn - 1) // ppn
+    if placement == "block":
+        node = lambda p: p // ppn
+        lrank = lambda p: p % ppn
+    else:
+        node = lambda p: p % NN
+        lrank = lambda p: p // NN
+    members = lambda m: [s for s in range(R) if node(s) == m]
+
+    def partner(q, m):
+        mem = members(m)
+        want = lrank(q) % len(mem)
+        return [s for s in mem if lrank(s) == want][0]
+    return node, members, partner, NN
+
+
+PLACEMENTS = ["block", "cyclic"]
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -56,10 +78,11 @@ def test_halo_matches_brute_force(case):
         assert list(halos[r]) == brute_halo(rs, rp, cols, r)
 
 
+@pytest.mark.parametrize("placement", PLACEMENTS)
 @pytest.mark.parametrize("variant", ["plain", "locality"])
 @pytest.mark.parametrize("case", CASES)
-def test_exchange_equals_direct_global_gather(case, variant):
-    rs, rp, cols, halos, D = build(case)
+def test_exchange_equals_direct_global_gather(case, variant, placement):
+    rs, rp, cols, halos, D = build(case, placement)
     R = len(rs) - 1
     n = int(rs[-1])
     plans = [D.plan(r, variant) for r in range(R)]
@@ -94,14 +117,15 @@ def test_plain_symmetry_and_conservation(case):
         assert np.all(p["s1_counts"] > 0) and np.all(p["r1_counts"] > 0)
 
 
+@pytest.mark.parametrize("placement", PLACEMENTS)
 @pytest.mark.parametrize("case", CASES)
-def test_locality_dedup_and_routing(case):
+def test_locality_dedup_and_routing(case, placement):
     """A value crosses from rank q to node m at most once, all of node m's needs
     from q cross, inter-node traffic only goes to partners, forwarding stays
     on-node, and every halo entry is delivered exactly once."""
-    rs, rp, cols, halos, D = build(case)
+    rs, rp, cols, halos, D = build(case, placement)
     R = len(rs) - 1
-    node = lambda p: p // D.ppn
+    node, members, partner, NN = placement_fns(R, D.ppn, placement)
     plans = [D.locality_plan(r) for r in range(R)]
     need = [set(brute_halo(rs, rp, cols, r)) for r in range(R)]
     for q in range(R):
@@ -112,14 +136,15 @@ def test_locality_dedup_and_routing(case):
             assert len(vals) == len(set(vals))
             if node(t) != node(q):
                 assert node(t) not in inter          # one message per remote node
+                assert t == partner(q, node(t))      # to the partner on that node
                 inter[node(t)] = set(vals)
             else:
                 assert set(vals) == {x for x in need[t] if rs[q] <= x < rs[q + 1]}
-        for m in range((R + D.ppn - 1) // D.ppn):
+        for m in range(NN):
             if m == node(q):
                 continue
             want = set()
-            for s in range(m * D.ppn, min(R, (m + 1) * D.ppn)):
+            for s in members(m):
                 want |= {x for x in need[s] if rs[q] <= x < rs[q + 1]}
             assert inter.get(m, set()) == want
         for t in p["s2_procs"]:
@@ -142,15 +167,16 @@ def test_locality_dedup_and_routing(case):
         assert direct + self_ + out["recv2"][r].shape[0] == halos[r].size
 
 
+@pytest.mark.parametrize("placement", PLACEMENTS)
 @pytest.mark.parametrize("case", [c for c in CASES])
-def test_locality_special_cases(case):
+def test_locality_special_cases(case, placement):
     """ppn == 1 (every neighbor remote, nothing to merge) and one node (no
     inter-node traffic) both reduce the 2-step plan to the plain plan."""
     n, R, mx, pf, seed, uneven, _ = case
     rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
     halos = P.all_halos(rp, cols, rs)
     for ppn in (1, R, R + 3):
-        D = P.Decomposition(halos, rs, ppn)
+        D = P.Decomposition(halos, rs, ppn, placement)
         for r in range(R):
             a, b = D.plain_plan(r), D.locality_plan(r)
             for k in P.PLAN_KEYS:
@@ -232,12 +258,12 @@ def test_backward_is_adjoint_of_forward(case):
 @settings(max_examples=25, deadline=None)
 @given(n=st.integers(1, 120), R=st.integers(1, 12), mx=st.integers(1, 6),
        pf=st.floats(0.0, 1.0), seed=st.integers(0, 10_000), uneven=st.booleans(),
-       ppn=st.integers(1, 6))
-def test_random_decompositions(n, R, mx, pf, seed, uneven, ppn):
+       ppn=st.integers(1, 6), placement=st.sampled_from(PLACEMENTS))
+def test_random_decompositions(n, R, mx, pf, seed, uneven, ppn, placement):
     R = min(R, n)
     rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
     halos = P.all_halos(rp, cols, rs)
-    D = P.Decomposition(halos, rs, ppn)
+    D = P.Decomposition(halos, rs, ppn, placement)
     x = uniform_pm1(seed + 1, n).reshape(n, 1)
     for variant in ("plain", "locality"):
         plans = [D.plan(r, variant) for r in range(R)]
@@ -270,7 +296,7 @@ def _fold(terms):
     return acc
 
 
-def brute_staged_expression(halos, row_starts, ppn):
+def brute_staged_expression(halos, row_starts, ppn, placement="block"):
     """Expected expression of every row's gradient under reading R15, built
     from the definitions alone: the owner p sends row c once to each on-node
     rank that needs it and once per remote node m that needs it, to the
@@ -278,6 +304,7 @@ def brute_staged_expression(halos, row_starts, ppn):
     first, then its node's other needers in ascending rank; the owner adds
     its send slots in ascending destination rank."""
     R = len(row_starts) - 1
+    node, _, partner, _ = placement_fns(R, ppn, placement)
     needers = {}
     for s, h in enumerate(halos):
         for c in np.asarray(h).tolist():
@@ -285,15 +312,14 @@ def brute_staged_expression(halos, row_starts, ppn):
     out = {}
     for c, ss in needers.items():
         p = int(np.searchsorted(row_starts, c, side="right") - 1)
-        node_p = p // ppn
+        node_p = node(p)
         slots = {}
         for s in ss:
-            m = s // ppn
+            m = node(s)
             if m == node_p:
                 slots[s] = [s]
             else:
-                cnt = min(ppn, R - m * ppn)
-                t = m * ppn + (p % ppn) % cnt
+                t = partner(p, m)
                 slots.setdefault(t, [])
                 slots[t].append(s)
         terms = []
@@ -305,18 +331,19 @@ def brute_staged_expression(halos, row_starts, ppn):
     return out
 
 
+@pytest.mark.parametrize("placement", PLACEMENTS)
 @pytest.mark.parametrize("variant", ["plain", "locality"])
 @pytest.mark.parametrize("case", CASES)
-def test_staged_adjoint_order_brute_force(case, variant):
+def test_staged_adjoint_order_brute_force(case, variant, placement):
     """Every row's gradient is the sum the reading prescribes, term for term
     and in that grouping (symbolic values), for both plans."""
-    rs, rp, cols, halos, D = build(case)
+    rs, rp, cols, halos, D = build(case, placement)
     n, R = int(rs[-1]), len(rs) - 1
     ppn = case[-1] if variant == "locality" else 1   # the plain plan = one rank per node
     plans = [D.plan(r, variant) for r in range(R)]
     gy = [np.array([Sym(f"g{r}_{c}") for c in np.asarray(h).tolist()], dtype=object) for r, h in enumerate(halos)]
     got = M.staged_adjoint_reference(plans, gy, rs)["g_x"]
-    want = brute_staged_expression(halos, rs, ppn)
+    want = brute_staged_expression(halos, rs, ppn, placement)
     for c in range(n):
         if c in want:
             assert got[c] == want[c], (c, got[c], want[c])
