@@ -71,6 +71,24 @@ typedef enum { HX_F32 = 0, HX_F64 = 1 } hx_dtype;
  * decomposition batches only (hx_req_from_plan returns HX_ERR_UNSUPPORTED). */
 typedef enum { HX_PLAIN = 0, HX_LOCALITY_2STEP = 1, HX_LOCALITY_3STEP = 2 } hx_variant;
 
+/* Placement of nranks ranks on NN = ceil(nranks / ppn) nodes (Sec. 2.2 groups
+ * the ranks of a node without fixing which ranks share one).
+ * HX_NODES_BLOCK: node(p) = p / ppn, local rank p mod ppn; the last node may
+ * hold fewer ranks.  HX_NODES_CYCLIC (round robin): node(p) = p mod NN, local
+ * rank p / NN.  Under either map the partner of rank q on node m is the rank
+ * of node m whose local rank is lrank(q) mod (ranks on node m). */
+typedef enum { HX_NODES_BLOCK = 0, HX_NODES_CYCLIC = 1 } hx_node_map;
+
+/* Options of a plan (the info argument of a persistent init, Listing 4):
+ * variant; ppn >= 1 ranks per node (ignored by HX_PLAIN); node_map (the
+ * 3-step variant needs HX_NODES_BLOCK, since its aggregator packs its node's
+ * rows as one contiguous range; HX_ERR_UNSUPPORTED otherwise). */
+typedef struct {
+  hx_variant variant;
+  int ppn;
+  hx_node_map node_map;
+} hx_info;
+
 typedef struct hx_topo hx_topo;
 typedef struct hx_plan hx_plan;
 typedef struct hx_req hx_req;
@@ -201,7 +219,11 @@ int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local,
 
 /* ---------------------------------------------------------------------------
  * Plans of a whole decomposition, built on the GPU (all setup at init,
- * Sec. 2.2), for the plain variant or the 2-step locality-aware variant.
+ * Sec. 2.2), for the plain variant or the locality-aware variants.  This is
+ * the collective half of the locality-aware init: every rank's halo goes in
+ * at once, since deduplication over a node and the partner assignment need
+ * the halos of all ranks; hx_req_from_plan then gives one rank its request
+ * (the per-rank half).
  *
  * hx_plan_from_csr: halo discovery from the sparse structure, then as below.
  *   row_starts host [nranks+1] int64, increasing, row_starts[0] = 0, n = row_starts[nranks];
@@ -214,19 +236,20 @@ int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local,
  * For each rank the plan holds (the lists a persistent init would build):
  *   halo, stage-1 send/recv lists (plain: all messages; locality: on-node
  *   messages plus one deduplicated message per remote node, sent to the
- *   rank with the same local rank there), stage-2 (redistribution) lists,
+ *   partner there), stage-2 (redistribution) lists,
  *   the unpack map into the halo, and the transpose of the pack map.
- * ppn >= 1 ranks per node (ignored by HX_PLAIN).  The plan owns its device
- * arrays; inputs are read during the call only.  The call synchronises
- * stream before returning.  Errors: HX_ERR_ARG, HX_ERR_RANGE (column out of
+ * info (host, read during the call): variant, ranks per node and node map.
+ * The plan owns its device arrays; inputs are read during the call only.
+ * The call synchronises stream before returning.  Errors: HX_ERR_ARG (null
+ * info, ppn < 1, unknown variant or node map), HX_ERR_RANGE (column out of
  * range, halo not strictly increasing or owned by its rank),
- * HX_ERR_UNSUPPORTED (sizes beyond int32 or the dense rank-pair tables
- * exceeding HX_PLAN_MAX_RANKS ranks).
+ * HX_ERR_UNSUPPORTED (sizes beyond int32, the dense rank-pair tables
+ * exceeding HX_PLAN_MAX_RANKS ranks, the 3-step variant with a cyclic map).
  * ------------------------------------------------------------------------- */
 #define HX_PLAN_MAX_RANKS 16384
-int hx_plan_from_csr(int nranks, const int64_t* row_starts, int ppn, hx_variant variant,
+int hx_plan_from_csr(int nranks, const int64_t* row_starts, const hx_info* info,
                      const int64_t* row_ptr, const int32_t* cols, void* stream, hx_plan** out);
-int hx_plan_from_halos(int nranks, const int64_t* row_starts, int ppn, hx_variant variant,
+int hx_plan_from_halos(int nranks, const int64_t* row_starts, const hx_info* info,
                        const int64_t* halo_ptr, const int32_t* halo_cols, void* stream,
                        hx_plan** out);
 int hx_plan_free(hx_plan** plan);

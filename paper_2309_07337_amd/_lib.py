@@ -19,6 +19,8 @@ HX_SUCCESS = 0
 HX_ERR_ARG, HX_ERR_RANGE, HX_ERR_STATE, HX_ERR_NOMEM, HX_ERR_UNSUPPORTED, HX_ERR_HIP = -1, -2, -3, -4, -5, -6
 HX_F32, HX_F64 = 0, 1
 HX_PLAIN, HX_LOCALITY_2STEP, HX_LOCALITY_3STEP = 0, 1, 2
+HX_NODES_BLOCK, HX_NODES_CYCLIC = 0, 1
+NODE_MAPS = {"block": HX_NODES_BLOCK, "cyclic": HX_NODES_CYCLIC}
 HX_ARENA_SEND, HX_ARENA_RECV, HX_ARENA_GRAD_SEND = 0, 1, 4
 HX_WORLD_SIM_TRANSFER, HX_WORLD_STAGED_BACKWARD = 1, 2
 HX_REPLAY_GRAPH, HX_REPLAY_DIRECT = 0, 1
@@ -61,6 +63,10 @@ class hx_sched(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class hx_info(C.Structure):
+    _fields_ = [("variant", C.c_int), ("ppn", C.c_int), ("node_map", C.c_int)]
+
+
 _lib = None
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -88,8 +94,8 @@ def load() -> C.CDLL:
         "hx_topo_free": (C.c_int, [PP]),
         "hx_neighbor_alltoallv_init": (C.c_int, [VP, C.c_int64, I32P, I32P, I32P, VP, I32P, I32P, C.c_int,
                                                  C.c_int, VP, PP]),
-        "hx_plan_from_csr": (C.c_int, [C.c_int, I64P, C.c_int, C.c_int, VP, VP, VP, PP]),
-        "hx_plan_from_halos": (C.c_int, [C.c_int, I64P, C.c_int, C.c_int, I64P, VP, VP, PP]),
+        "hx_plan_from_csr": (C.c_int, [C.c_int, I64P, C.POINTER(hx_info), VP, VP, VP, PP]),
+        "hx_plan_from_halos": (C.c_int, [C.c_int, I64P, C.POINTER(hx_info), I64P, VP, VP, PP]),
         "hx_plan_free": (C.c_int, [PP]),
         "hx_plan_field_size": (C.c_int, [VP, C.c_int, C.c_int, I64P]),
         "hx_plan_field_copy": (C.c_int, [VP, C.c_int, C.c_int, I32P]),
@@ -311,19 +317,29 @@ def hx_neighbor_alltoallv_init(x_local, sendcounts, sdispls, send_idx, halo, rec
     return Req(out, keep=(x_local, halo, topo))
 
 
-def hx_plan_from_csr(nranks: int, row_starts, ppn: int, variant: int, row_ptr, cols, stream=None) -> Plan:
+def _info(ppn: int, variant: int, node_map) -> hx_info:
+    nm = NODE_MAPS[node_map] if isinstance(node_map, str) else int(node_map)
+    return hx_info(int(variant), int(ppn), nm)
+
+
+def hx_plan_from_csr(nranks: int, row_starts, ppn: int, variant: int, row_ptr, cols, stream=None,
+                     node_map="block") -> Plan:
+    """node_map: "block" / "cyclic" (or HX_NODES_*); with ppn and variant it
+    fills the hx_info argument."""
     rs = _i64(row_starts)
+    info = _info(ppn, variant, node_map)
     out = C.c_void_p()
-    _check(load().hx_plan_from_csr(nranks, _p64(rs), ppn, variant, _dptr(row_ptr), _dptr(cols),
+    _check(load().hx_plan_from_csr(nranks, _p64(rs), C.byref(info), _dptr(row_ptr), _dptr(cols),
                                    _stream(stream), C.byref(out)))
     return Plan(out)
 
 
 def hx_plan_from_halos(nranks: int, row_starts, ppn: int, variant: int, halo_ptr, halo_cols,
-                       stream=None) -> Plan:
+                       stream=None, node_map="block") -> Plan:
     rs, hp = _i64(row_starts), _i64(halo_ptr)
+    info = _info(ppn, variant, node_map)
     out = C.c_void_p()
-    _check(load().hx_plan_from_halos(nranks, _p64(rs), ppn, variant, _p64(hp), _dptr(halo_cols),
+    _check(load().hx_plan_from_halos(nranks, _p64(rs), C.byref(info), _p64(hp), _dptr(halo_cols),
                                      _stream(stream), C.byref(out)))
     return Plan(out)
 

@@ -42,6 +42,7 @@ struct hx_req {
 struct hx_plan {
   int R = 0;
   int ppn = 1;
+  int node_map = HX_NODES_BLOCK;
   int variant = HX_PLAIN;
   int64_t n = 0;
   std::vector<int64_t> row_starts;               // host [R+1]

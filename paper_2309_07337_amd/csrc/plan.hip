@@ -49,25 +49,36 @@ __device__ __forceinline__ int upper_rank(const int64_t* __restrict__ starts, in
   return lo;
 }
 
-__device__ __forceinline__ int node_cnt(int m, int ppn, int R) { return min(ppn, R - m * ppn); }
-__device__ __forceinline__ int partner_of(int q, int m, int ppn, int R) {
-  return m * ppn + (q % ppn) % node_cnt(m, ppn, R);
-}
-// 3-step (one message per node pair): the rank of node n that sends node n's
-// data for node m, and the rank of node m that receives it.
-__device__ __forceinline__ int aggr_of(int n, int m, int ppn, int R) { return n * ppn + m % node_cnt(n, ppn, R); }
-__device__ __forceinline__ int recv_of(int n, int m, int ppn, int R) { return m * ppn + n % node_cnt(m, ppn, R); }
+// Placement of R ranks on NN = ceil(R / ppn) nodes (Sec. 2.2 groups ranks by
+// node without fixing which ranks share one).  Block: node p / ppn, local rank
+// p % ppn, the last node may hold fewer ranks.  Cyclic (round robin): node
+// p % NN, local rank p / NN.
+struct Place {
+  int R, ppn, NN, cyc;
+  __device__ int node(int p) const { return cyc ? p % NN : p / ppn; }
+  __device__ int lrank(int p) const { return cyc ? p / NN : p % ppn; }
+  __device__ int cnt(int m) const { return cyc ? (R - 1 - m) / NN + 1 : min(ppn, R - m * ppn); }
+  __device__ int rank_at(int m, int l) const { return cyc ? l * NN + m : m * ppn + l; }
+  // The rank of node m that receives rank q's deduplicated message: the one
+  // whose local rank is q's modulo the size of node m.
+  __device__ int partner(int q, int m) const { return rank_at(m, lrank(q) % cnt(m)); }
+};
+
+// 3-step (one message per node pair, block placement only): the rank of node
+// n that sends node n's data for node m, and the rank of node m that receives it.
+__device__ __forceinline__ int aggr_of(const Place& P, int n, int m) { return P.rank_at(n, m % P.cnt(n)); }
+__device__ __forceinline__ int recv_of(const Place& P, int n, int m) { return P.rank_at(m, n % P.cnt(m)); }
 // The forwarder on node m of the entries owned by rank q (the rank their
 // aggregated stage-1 message lands on), the sender of that message, and the
 // first row of the column range the message deduplicates over.
-__device__ __forceinline__ int fwd_of(int q, int m, int ppn, int R, int v3) {
-  return v3 ? recv_of(q / ppn, m, ppn, R) : partner_of(q, m, ppn, R);
+__device__ __forceinline__ int fwd_of(const Place& P, int q, int m, int v3) {
+  return v3 ? recv_of(P, P.node(q), m) : P.partner(q, m);
 }
-__device__ __forceinline__ int agg_sender(int q, int m, int ppn, int R, int v3) {
-  return v3 ? aggr_of(q / ppn, m, ppn, R) : q;
+__device__ __forceinline__ int agg_sender(const Place& P, int q, int m, int v3) {
+  return v3 ? aggr_of(P, P.node(q), m) : q;
 }
-__device__ __forceinline__ int64_t agg_base(int q, const int64_t* __restrict__ rs, int ppn, int v3) {
-  return v3 ? rs[(q / ppn) * ppn] : rs[q];
+__device__ __forceinline__ int64_t agg_base(const Place& P, int q, const int64_t* __restrict__ rs, int v3) {
+  return v3 ? rs[P.rank_at(P.node(q), 0)] : rs[q];
 }
 
 template <class T>
@@ -383,10 +394,10 @@ __global__ void k_row_compact(const int32_t* __restrict__ A, const int32_t* __re
 // Locality-aware (2-step) tables
 // ---------------------------------------------------------------------------
 __global__ void k_node_mark(const int32_t* __restrict__ hcol, const int32_t* __restrict__ hrank, int64_t nH,
-                            int ppn, uint32_t* NB, int64_t W1) {
+                            Place P, uint32_t* NB, int64_t W1) {
   GRID_STRIDE(e, nH) {
     const int64_t c = hcol[e];
-    const int m = hrank[e] / ppn;
+    const int m = P.node(hrank[e]);
     atomicOr(NB + (size_t)m * W1 + (c >> 5), 1u << (c & 31));
   }
 }
@@ -408,19 +419,21 @@ __global__ void k_word_exscan(const uint32_t* __restrict__ NB, int64_t W1, int32
 // MD[m][q] = |D(q -> m)| for q off node m (else 0).  3-step: |D(n -> m)| of
 // q's node n at q = the pair's aggregator (else 0).
 __global__ void k_dedup_counts(const uint32_t* __restrict__ NB, const int32_t* __restrict__ NBP, int64_t W1,
-                               const int64_t* __restrict__ rs, int R, int NN, int ppn, int v3, int32_t* MD) {
-  GRID_STRIDE(i, (int64_t)NN * R) {
+                               const int64_t* __restrict__ rs, Place P, int v3, int32_t* MD) {
+  const int R = P.R;
+  GRID_STRIDE(i, (int64_t)P.NN * R) {
     const int m = (int)(i / R), q = (int)(i % R);
     int32_t v = 0;
-    if (q / ppn != m) {
+    if (P.node(q) != m) {
       const uint32_t* nb = NB + (size_t)m * W1;
       const int32_t* np = NBP + (size_t)m * W1;
       if (!v3) {
         v = bit_rank(nb, np, rs[q + 1]) - bit_rank(nb, np, rs[q]);
       } else {
-        const int n = q / ppn;
-        if (q == aggr_of(n, m, ppn, R))
-          v = bit_rank(nb, np, rs[min(R, (n + 1) * ppn)]) - bit_rank(nb, np, rs[n * ppn]);
+        const int n = P.node(q);
+        const int first = P.rank_at(n, 0);  // block: node n's rows are contiguous
+        if (q == aggr_of(P, n, m))
+          v = bit_rank(nb, np, rs[first + P.cnt(n)]) - bit_rank(nb, np, rs[first]);
       }
     }
     MD[i] = v;
@@ -428,15 +441,16 @@ __global__ void k_dedup_counts(const uint32_t* __restrict__ NB, const int32_t* _
 }
 
 // Stage-1 message sizes S1[q][d]: direct to on-node d, deduplicated to partners.
-__global__ void k_stage1_sizes(const int32_t* __restrict__ MT, const int32_t* __restrict__ MD, int R, int ppn,
-                               int v3, int32_t* S1) {
+__global__ void k_stage1_sizes(const int32_t* __restrict__ MT, const int32_t* __restrict__ MD, Place P, int v3,
+                               int32_t* S1) {
+  const int R = P.R;
   GRID_STRIDE(i, (int64_t)R * R) {
     const int q = (int)(i / R), d = (int)(i % R);
     int32_t v = 0;
     if (d != q) {
-      const int nq = q / ppn, nd = d / ppn;
+      const int nq = P.node(q), nd = P.node(d);
       if (nq == nd) v = MT[i];
-      else if (v3 ? (q == aggr_of(nq, nd, ppn, R) && d == recv_of(nq, nd, ppn, R)) : d == partner_of(q, nd, ppn, R))
+      else if (v3 ? (q == aggr_of(P, nq, nd) && d == recv_of(P, nq, nd)) : d == P.partner(q, nd))
         v = MD[(size_t)nd * R + q];
     }
     S1[i] = v;
@@ -445,23 +459,24 @@ __global__ void k_stage1_sizes(const int32_t* __restrict__ MT, const int32_t* __
 
 // Stage-2 message sizes S2[t][s] (t forwards to s on its node): the entries of
 // N_s owned by remote ranks whose aggregated message lands on t.
-__global__ void k_stage2_sizes(const int32_t* __restrict__ M, int R, int ppn, int NN, int v3, int32_t* S2) {
+__global__ void k_stage2_sizes(const int32_t* __restrict__ M, Place P, int v3, int32_t* S2) {
+  const int R = P.R;
   GRID_STRIDE(i, (int64_t)R * R) {
     const int t = (int)(i / R), s = (int)(i % R);
     int64_t v = 0;
-    const int n = t / ppn;
-    if (s != t && s / ppn == n) {
-      const int cn = node_cnt(n, ppn, R);
-      const int lt = t % ppn;
+    const int n = P.node(t);
+    if (s != t && P.node(s) == n) {
+      const int cn = P.cnt(n);
+      const int lt = P.lrank(t);
       const int32_t* Ms = M + (size_t)s * R;
-      for (int m = 0; m < NN; ++m) {
+      for (int m = 0; m < P.NN; ++m) {
         if (m == n) continue;
-        const int cm = node_cnt(m, ppn, R);
+        const int cm = P.cnt(m);
         if (v3) {  // every rank of the nodes whose pair message lands on t
           if (m % cn == lt)
-            for (int l = 0; l < cm; ++l) v += Ms[m * ppn + l];
+            for (int l = 0; l < cm; ++l) v += Ms[P.rank_at(m, l)];
         } else {
-          for (int l = lt; l < cm; l += cn) v += Ms[m * ppn + l];
+          for (int l = lt; l < cm; l += cn) v += Ms[P.rank_at(m, l)];
         }
       }
     }
@@ -470,29 +485,42 @@ __global__ void k_stage2_sizes(const int32_t* __restrict__ M, int R, int ppn, in
 }
 
 // QP[s][q]: for q off s's node, the number of entries of N_s owned by the
-// ranks before q (ascending) that share q's partner on s's node.
-__global__ void k_class_prefix(const int32_t* __restrict__ M, int R, int ppn, int NN, int v3, int32_t* QP) {
-  GRID_STRIDE(i, (int64_t)R * ppn) {
-    const int s = (int)(i / ppn), l0 = (int)(i % ppn);
-    const int n = s / ppn;
-    const int cn = node_cnt(n, ppn, R);
+// ranks before q (ascending) that share q's partner on s's node.  Class l0 of
+// node n: the remote ranks whose local rank is l0 modulo the size of node n
+// (3-step: every rank of the nodes m with m mod cn == l0).
+__global__ void k_class_prefix(const int32_t* __restrict__ M, Place P, int v3, int32_t* QP) {
+  const int R = P.R;
+  GRID_STRIDE(i, (int64_t)R * P.ppn) {
+    const int s = (int)(i / P.ppn), l0 = (int)(i % P.ppn);
+    const int n = P.node(s);
+    const int cn = P.cnt(n);
     if (l0 >= cn) continue;
     const int32_t* Ms = M + (size_t)s * R;
     int32_t* Qs = QP + (size_t)s * R;
     int32_t run = 0;
-    for (int m = 0; m < NN; ++m) {
+    if (P.cyc) {  // rank l*NN + m ascends with the local rank first, then the node
+      for (int l = l0; l < P.ppn; l += cn)
+        for (int m = 0; m < P.NN; ++m) {
+          if (m == n || l >= P.cnt(m)) continue;
+          const int q = P.rank_at(m, l);
+          Qs[q] = run;
+          run += Ms[q];
+        }
+      continue;
+    }
+    for (int m = 0; m < P.NN; ++m) {  // block: rank m*ppn + l ascends with the node first
       if (m == n) continue;
-      const int cm = node_cnt(m, ppn, R);
-      if (v3) {  // class l0: the nodes m with m mod cn == l0, every rank of each
+      const int cm = P.cnt(m);
+      if (v3) {
         if (m % cn != l0) continue;
         for (int l = 0; l < cm; ++l) {
-          const int q = m * ppn + l;
+          const int q = P.rank_at(m, l);
           Qs[q] = run;
           run += Ms[q];
         }
       } else {
         for (int l = l0; l < cm; l += cn) {
-          const int q = m * ppn + l;
+          const int q = P.rank_at(m, l);
           Qs[q] = run;
           run += Ms[q];
         }
@@ -508,28 +536,30 @@ __global__ void k_class_prefix(const int32_t* __restrict__ M, int R, int ppn, in
 // the on-node ones (locality).
 __global__ void k_s1_direct(const int32_t* __restrict__ hcol, const int32_t* __restrict__ hrank,
                             const int32_t* __restrict__ own, int64_t nH, const int64_t* __restrict__ hoff,
-                            const int64_t* __restrict__ rs, int R, int ppn, int onnode_only, int v3,
+                            const int64_t* __restrict__ rs, Place P, int onnode_only, int v3,
                             const int32_t* __restrict__ PS1, const int32_t* __restrict__ PM,
                             const int64_t* __restrict__ s1_off, int32_t* s1_idx, int* err) {
+  const int R = P.R;
   GRID_STRIDE(e, nH) {
     const int s = hrank[e], q = own[e];
-    if (onnode_only && q / ppn != s / ppn) continue;
+    if (onnode_only && P.node(q) != P.node(s)) continue;
     const int64_t j = e - hoff[s];
     const int64_t pos = s1_off[q] + PS1[(size_t)q * R + s] + (j - PM[(size_t)s * R + q]);
     if (pos < s1_off[q] || pos >= s1_off[q + 1]) {
       atomicOr(err, 32);
       continue;
     }
-    s1_idx[pos] = (int32_t)(hcol[e] - agg_base(q, rs, ppn, v3));  // 3-step: rows of the node
+    s1_idx[pos] = (int32_t)(hcol[e] - agg_base(P, q, rs, v3));  // 3-step: rows of the node
   }
 }
 
 // Stage-1 aggregated entries: one per set bit of a node bitmap owned off-node.
 __global__ void k_s1_agg(const uint32_t* __restrict__ NB, const int32_t* __restrict__ NBP, int64_t W1,
-                         int64_t W, int NN, const int64_t* __restrict__ rs, int R, int ppn, int v3,
+                         int64_t W, const int64_t* __restrict__ rs, Place P, int v3,
                          const int32_t* __restrict__ PS1, const int64_t* __restrict__ s1_off, int32_t* s1_idx,
                          int* err) {
-  GRID_STRIDE(i, (int64_t)NN * W) {
+  const int R = P.R;
+  GRID_STRIDE(i, (int64_t)P.NN * W) {
     const int m = (int)(i / W);
     const int64_t w = i % W;
     const uint32_t* nb = NB + (size_t)m * W1;
@@ -540,10 +570,10 @@ __global__ void k_s1_agg(const uint32_t* __restrict__ NB, const int32_t* __restr
       bits &= bits - 1u;
       const int64_t c = w * 32 + b;
       const int q = upper_rank(rs, R, c);
-      if (q / ppn == m) continue;
-      const int t = fwd_of(q, m, ppn, R, v3);
-      const int a = agg_sender(q, m, ppn, R, v3);
-      const int64_t base = agg_base(q, rs, ppn, v3);
+      if (P.node(q) == m) continue;
+      const int t = fwd_of(P, q, m, v3);
+      const int a = agg_sender(P, q, m, v3);
+      const int64_t base = agg_base(P, q, rs, v3);
       const int64_t pos = s1_off[a] + PS1[(size_t)a * R + t] + (bit_rank(nb, np, c) - bit_rank(nb, np, base));
       if (pos < s1_off[a] || pos >= s1_off[a + 1]) {
         atomicOr(err, 32);
@@ -558,16 +588,17 @@ __global__ void k_s1_agg(const uint32_t* __restrict__ NB, const int32_t* __restr
 // aggregated message landed on another rank t of s's node.
 __global__ void k_s2_src(const int32_t* __restrict__ hcol, const int32_t* __restrict__ hrank,
                          const int32_t* __restrict__ own, int64_t nH, const int64_t* __restrict__ hoff,
-                         const int64_t* __restrict__ rs, int R, int ppn, const int32_t* __restrict__ PS2,
+                         const int64_t* __restrict__ rs, Place P, const int32_t* __restrict__ PS2,
                          const int32_t* __restrict__ QP, const int32_t* __restrict__ PM,
                          const int32_t* __restrict__ PR1, const uint32_t* __restrict__ NB,
                          const int32_t* __restrict__ NBP, int64_t W1, const int64_t* __restrict__ s2_off,
                          int v3, int32_t* s2_src, int* err) {
+  const int R = P.R;
   GRID_STRIDE(e, nH) {
     const int s = hrank[e], q = own[e];
-    const int n = s / ppn;
-    if (q / ppn == n) continue;
-    const int t = fwd_of(q, n, ppn, R, v3);
+    const int n = P.node(s);
+    if (P.node(q) == n) continue;
+    const int t = fwd_of(P, q, n, v3);
     if (t == s) continue;
     const int64_t j = e - hoff[s];
     const int64_t c = hcol[e];
@@ -578,19 +609,20 @@ __global__ void k_s2_src(const int32_t* __restrict__ hcol, const int32_t* __rest
       atomicOr(err, 32);
       continue;
     }
-    s2_src[pos] = PR1[(size_t)t * R + agg_sender(q, n, ppn, R, v3)] +
-                  (bit_rank(nb, np, c) - bit_rank(nb, np, agg_base(q, rs, ppn, v3)));
+    s2_src[pos] = PR1[(size_t)t * R + agg_sender(P, q, n, v3)] +
+                  (bit_rank(nb, np, c) - bit_rank(nb, np, agg_base(P, q, rs, v3)));
   }
 }
 
 // Unpack map: slot of each halo entry in [stage-1 recv | stage-2 recv].
 __global__ void k_unpack_map(const int32_t* __restrict__ hcol, const int32_t* __restrict__ hrank,
                              const int32_t* __restrict__ own, int64_t nH, const int64_t* __restrict__ hoff,
-                             const int64_t* __restrict__ rs, int R, int ppn, int locality, int v3,
+                             const int64_t* __restrict__ rs, Place P, int locality, int v3,
                              const int32_t* __restrict__ PM, const int32_t* __restrict__ PR1,
                              const int32_t* __restrict__ PR2, const int32_t* __restrict__ QP,
                              const uint32_t* __restrict__ NB, const int32_t* __restrict__ NBP, int64_t W1,
                              const int64_t* __restrict__ r1_tot, int32_t* unpack) {
+  const int R = P.R;
   GRID_STRIDE(e, nH) {
     const int r = hrank[e];
     const int64_t j = e - hoff[r];
@@ -599,18 +631,18 @@ __global__ void k_unpack_map(const int32_t* __restrict__ hcol, const int32_t* __
       continue;
     }
     const int q = own[e];
-    const int n = r / ppn;
+    const int n = P.node(r);
     const int64_t c = hcol[e];
     int64_t v;
-    if (q / ppn == n) {
+    if (P.node(q) == n) {
       v = PR1[(size_t)r * R + q] + (j - PM[(size_t)r * R + q]);
     } else {
-      const int t = fwd_of(q, n, ppn, R, v3);
+      const int t = fwd_of(P, q, n, v3);
       const uint32_t* nb = NB + (size_t)n * W1;
       const int32_t* np = NBP + (size_t)n * W1;
       if (t == r)
-        v = PR1[(size_t)r * R + agg_sender(q, n, ppn, R, v3)] +
-            (bit_rank(nb, np, c) - bit_rank(nb, np, agg_base(q, rs, ppn, v3)));
+        v = PR1[(size_t)r * R + agg_sender(P, q, n, v3)] +
+            (bit_rank(nb, np, c) - bit_rank(nb, np, agg_base(P, q, rs, v3)));
       else
         v = r1_tot[r] + PR2[(size_t)r * R + t] + QP[(size_t)r * R + q] + (j - PM[(size_t)r * R + q]);
     }
@@ -744,6 +776,7 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
   const bool loc = p->variant != HX_PLAIN;
   const int v3 = p->variant == HX_LOCALITY_3STEP ? 1 : 0;
   const int NN = (R + ppn - 1) / ppn;
+  const Place PL{R, ppn, NN, p->node_map == HX_NODES_CYCLIC ? 1 : 0};
   const int64_t W = (n + 31) / 32;
   const int64_t W1 = W + 1;
 
@@ -780,26 +813,26 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
     HX_TRY(NBP.alloc((size_t)NN * W1 * 4));
     if (nH > 0) {
       hipLaunchKernelGGL(k_node_mark, dim3(blocks_for(nH)), dim3(TB), 0, s, p->d[HX_F_HALO].as<int32_t>(),
-                         hrank.as<int32_t>(), nH, ppn, NB.as<uint32_t>(), W1);
+                         hrank.as<int32_t>(), nH, PL, NB.as<uint32_t>(), W1);
       HX_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_word_exscan, dim3(NN), dim3(TB), 0, s, NB.as<uint32_t>(), W1, NBP.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(MD.alloc((size_t)NN * R * 4));
     hipLaunchKernelGGL(k_dedup_counts, dim3(blocks_for((int64_t)NN * R)), dim3(TB), 0, s, NB.as<uint32_t>(),
-                       NBP.as<int32_t>(), W1, p->row_starts_d.as<int64_t>(), R, NN, ppn, v3, MD.as<int32_t>());
+                       NBP.as<int32_t>(), W1, p->row_starts_d.as<int64_t>(), PL, v3, MD.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(S1.A.alloc((size_t)R * R * 4));
     hipLaunchKernelGGL(k_stage1_sizes, dim3(blocks_for((int64_t)R * R)), dim3(TB), 0, s, MT.as<int32_t>(),
-                       MD.as<int32_t>(), R, ppn, v3, S1.A.as<int32_t>());
+                       MD.as<int32_t>(), PL, v3, S1.A.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(S2.A.alloc((size_t)R * R * 4));
-    hipLaunchKernelGGL(k_stage2_sizes, dim3(blocks_for((int64_t)R * R)), dim3(TB), 0, s, M.A.as<int32_t>(), R,
-                       ppn, NN, v3, S2.A.as<int32_t>());
+    hipLaunchKernelGGL(k_stage2_sizes, dim3(blocks_for((int64_t)R * R)), dim3(TB), 0, s, M.A.as<int32_t>(), PL,
+                       v3, S2.A.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(zeros(&QP, (size_t)R * R * 4, s));
-    hipLaunchKernelGGL(k_class_prefix, dim3(blocks_for((int64_t)R * ppn)), dim3(TB), 0, s, M.A.as<int32_t>(), R,
-                       ppn, NN, v3, QP.as<int32_t>());
+    hipLaunchKernelGGL(k_class_prefix, dim3(blocks_for((int64_t)R * ppn)), dim3(TB), 0, s, M.A.as<int32_t>(), PL,
+                       v3, QP.as<int32_t>());
     HX_HIP(hipGetLastError());
     HX_TRY(dense_transpose(S1.A, &R1.A, R, s));
     HX_TRY(dense_transpose(S2.A, &R2.A, R, s));
@@ -852,21 +885,21 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
   if (nH > 0) {
     hipLaunchKernelGGL(k_s1_direct, dim3(blocks_for(nH)), dim3(TB), 0, s, p->d[HX_F_HALO].as<int32_t>(),
                        hrank.as<int32_t>(), own.as<int32_t>(), nH, hoff_d.as<int64_t>(),
-                       p->row_starts_d.as<int64_t>(), R, ppn, loc ? 1 : 0, v3, S1.P.as<int32_t>(), PM,
+                       p->row_starts_d.as<int64_t>(), PL, loc ? 1 : 0, v3, S1.P.as<int32_t>(), PM,
                        s1o_d.as<int64_t>(), p->d[HX_F_S1_IDX].as<int32_t>(), err.as<int>());
     HX_HIP(hipGetLastError());
   }
   if (loc) {
     if (NN * W > 0) {
       hipLaunchKernelGGL(k_s1_agg, dim3(blocks_for((int64_t)NN * W)), dim3(TB), 0, s, NB.as<uint32_t>(),
-                         NBP.as<int32_t>(), W1, W, NN, p->row_starts_d.as<int64_t>(), R, ppn, v3,
+                         NBP.as<int32_t>(), W1, W, p->row_starts_d.as<int64_t>(), PL, v3,
                          S1.P.as<int32_t>(), s1o_d.as<int64_t>(), p->d[HX_F_S1_IDX].as<int32_t>(), err.as<int>());
       HX_HIP(hipGetLastError());
     }
     if (nH > 0) {
       hipLaunchKernelGGL(k_s2_src, dim3(blocks_for(nH)), dim3(TB), 0, s, p->d[HX_F_HALO].as<int32_t>(),
                          hrank.as<int32_t>(), own.as<int32_t>(), nH, hoff_d.as<int64_t>(),
-                         p->row_starts_d.as<int64_t>(), R, ppn, S2.P.as<int32_t>(), QP.as<int32_t>(), PM,
+                         p->row_starts_d.as<int64_t>(), PL, S2.P.as<int32_t>(), QP.as<int32_t>(), PM,
                          R1.P.as<int32_t>(), NB.as<uint32_t>(), NBP.as<int32_t>(), W1, s2o_d.as<int64_t>(), v3,
                          p->d[HX_F_S2_SRC].as<int32_t>(), err.as<int>());
       HX_HIP(hipGetLastError());
@@ -875,7 +908,7 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
   if (nH > 0) {
     hipLaunchKernelGGL(k_unpack_map, dim3(blocks_for(nH)), dim3(TB), 0, s, p->d[HX_F_HALO].as<int32_t>(),
                        hrank.as<int32_t>(), own.as<int32_t>(), nH, hoff_d.as<int64_t>(),
-                       p->row_starts_d.as<int64_t>(), R, ppn, loc ? 1 : 0, v3, PM, R1.P.as<int32_t>(),
+                       p->row_starts_d.as<int64_t>(), PL, loc ? 1 : 0, v3, PM, R1.P.as<int32_t>(),
                        loc ? R2.P.as<int32_t>() : nullptr, loc ? QP.as<int32_t>() : nullptr,
                        loc ? NB.as<uint32_t>() : nullptr, loc ? NBP.as<int32_t>() : nullptr, W1,
                        r1t_d.as<int64_t>(), p->d[HX_F_UNPACK_SRC].as<int32_t>());
@@ -928,14 +961,20 @@ int build_from_halos(hx_plan* p, DevMem& hcol, const std::vector<int64_t>& hoff,
   return HX_SUCCESS;
 }
 
-int plan_common_checks(int nranks, const int64_t* row_starts, int ppn, hx_variant variant, hx_plan** out) {
+int plan_common_checks(int nranks, const int64_t* row_starts, const hx_info* info, hx_plan** out) {
   if (!out) return fail(HX_ERR_ARG, "null out");
   *out = nullptr;
+  if (!info) return fail(HX_ERR_ARG, "null info");
   if (nranks <= 0 || !row_starts) return fail(HX_ERR_ARG, "bad nranks / row_starts");
   if (nranks > HX_PLAN_MAX_RANKS) return fail(HX_ERR_UNSUPPORTED, "more than %d ranks", HX_PLAN_MAX_RANKS);
+  const hx_variant variant = info->variant;
   if (variant != HX_PLAIN && variant != HX_LOCALITY_2STEP && variant != HX_LOCALITY_3STEP)
     return fail(HX_ERR_ARG, "bad variant");
-  if (ppn < 1) return fail(HX_ERR_ARG, "ppn must be >= 1");
+  if (info->ppn < 1) return fail(HX_ERR_ARG, "ppn must be >= 1");
+  if (info->node_map != HX_NODES_BLOCK && info->node_map != HX_NODES_CYCLIC)
+    return fail(HX_ERR_ARG, "bad node map");
+  if (variant == HX_LOCALITY_3STEP && info->node_map != HX_NODES_BLOCK)
+    return fail(HX_ERR_UNSUPPORTED, "the 3-step variant needs block placement (a node's rows contiguous)");
   if (row_starts[0] != 0) return fail(HX_ERR_ARG, "row_starts[0] must be 0");
   for (int r = 0; r < nranks; ++r)
     if (row_starts[r + 1] < row_starts[r]) return fail(HX_ERR_ARG, "row_starts must be non-decreasing");
@@ -943,12 +982,13 @@ int plan_common_checks(int nranks, const int64_t* row_starts, int ppn, hx_varian
   return HX_SUCCESS;
 }
 
-int plan_alloc(int nranks, const int64_t* row_starts, int ppn, hx_variant variant, std::unique_ptr<hx_plan>* p) {
+int plan_alloc(int nranks, const int64_t* row_starts, const hx_info* info, std::unique_ptr<hx_plan>* p) {
   p->reset(new (std::nothrow) hx_plan);
   if (!*p) return fail(HX_ERR_NOMEM, "out of host memory");
   (*p)->R = nranks;
-  (*p)->ppn = variant == HX_PLAIN ? std::max(ppn, 1) : ppn;
-  (*p)->variant = variant;
+  (*p)->ppn = info->ppn;
+  (*p)->node_map = info->node_map;
+  (*p)->variant = info->variant;
   (*p)->n = row_starts[nranks];
   (*p)->row_starts.assign(row_starts, row_starts + nranks + 1);
   HX_TRY(upload_vec((*p)->row_starts_d, (*p)->row_starts));
@@ -1036,14 +1076,14 @@ using namespace hx;
 // ===========================================================================
 // Public plan API
 // ===========================================================================
-extern "C" int hx_plan_from_csr(int nranks, const int64_t* row_starts, int ppn, hx_variant variant,
+extern "C" int hx_plan_from_csr(int nranks, const int64_t* row_starts, const hx_info* info,
                                 const int64_t* row_ptr, const int32_t* cols, void* stream, hx_plan** out) {
-  HX_TRY(plan_common_checks(nranks, row_starts, ppn, variant, out));
+  HX_TRY(plan_common_checks(nranks, row_starts, info, out));
   const int64_t n = row_starts[nranks];
   if (n > 0 && !row_ptr) return fail(HX_ERR_ARG, "null row_ptr");
   hipStream_t s = (hipStream_t)stream;
   std::unique_ptr<hx_plan> p;
-  HX_TRY(plan_alloc(nranks, row_starts, ppn, variant, &p));
+  HX_TRY(plan_alloc(nranks, row_starts, info, &p));
   const int64_t W = (n + 31) / 32;
   const double bitmap_gb = (double)nranks * W * 4 / 1e9;
   if (bitmap_gb > 64.0) return fail(HX_ERR_UNSUPPORTED, "halo bitmaps would need %.1f GB", bitmap_gb);
@@ -1080,10 +1120,10 @@ extern "C" int hx_plan_from_csr(int nranks, const int64_t* row_starts, int ppn, 
   return HX_SUCCESS;
 }
 
-extern "C" int hx_plan_from_halos(int nranks, const int64_t* row_starts, int ppn, hx_variant variant,
+extern "C" int hx_plan_from_halos(int nranks, const int64_t* row_starts, const hx_info* info,
                                   const int64_t* halo_ptr, const int32_t* halo_cols, void* stream,
                                   hx_plan** out) {
-  HX_TRY(plan_common_checks(nranks, row_starts, ppn, variant, out));
+  HX_TRY(plan_common_checks(nranks, row_starts, info, out));
   if (!halo_ptr) return fail(HX_ERR_ARG, "null halo_ptr");
   if (halo_ptr[0] != 0) return fail(HX_ERR_ARG, "halo_ptr[0] must be 0");
   for (int r = 0; r < nranks; ++r)
@@ -1093,7 +1133,7 @@ extern "C" int hx_plan_from_halos(int nranks, const int64_t* row_starts, int ppn
   if (nH > 0 && !halo_cols) return fail(HX_ERR_ARG, "null halo_cols");
   hipStream_t s = (hipStream_t)stream;
   std::unique_ptr<hx_plan> p;
-  HX_TRY(plan_alloc(nranks, row_starts, ppn, variant, &p));
+  HX_TRY(plan_alloc(nranks, row_starts, info, &p));
   DevMem hcol;
   HX_TRY(hcol.alloc((size_t)nH * 4));
   if (nH) HX_HIP(hipMemcpyAsync(hcol.p, halo_cols, (size_t)nH * 4, hipMemcpyDeviceToDevice, s));

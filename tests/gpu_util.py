@@ -36,9 +36,9 @@ def variant_id(v: str) -> int:
     return {"plain": P.HX_PLAIN, "locality": P.HX_LOCALITY_2STEP, "locality3": P.HX_LOCALITY_3STEP}[v]
 
 
-def gpu_plan(rs, rp, cols, ppn, variant):
+def gpu_plan(rs, rp, cols, ppn, variant, node_map="block"):
     return P.hx_plan_from_csr(len(rs) - 1, rs, ppn, variant_id(variant), dev(np.asarray(rp, np.int64)),
-                              dev(np.asarray(cols, np.int32)))
+                              dev(np.asarray(cols, np.int32)), node_map=node_map)
 
 
 def plan_rank(plan, r) -> dict:

@@ -96,6 +96,19 @@ def test_plan_validation_on_host():
     with pytest.raises(P.HXError) as e:
         P.hx_plan_from_halos(2, [0, 2, 4], 0, P.HX_LOCALITY_2STEP, [0, 0, 0], None, stream=0)
     assert e.value.code == P.HX_ERR_ARG
+    # node map: unknown value, and the 3-step variant (contiguous node rows) under a cyclic map
+    with pytest.raises(P.HXError) as e:
+        P.hx_plan_from_halos(2, [0, 2, 4], 1, P.HX_LOCALITY_2STEP, [0, 0, 0], None, stream=0, node_map=7)
+    assert e.value.code == P.HX_ERR_ARG
+    with pytest.raises(P.HXError) as e:
+        P.hx_plan_from_halos(2, [0, 2, 4], 1, P.HX_LOCALITY_3STEP, [0, 0, 0], None, stream=0,
+                             node_map="cyclic")
+    assert e.value.code == P.HX_ERR_UNSUPPORTED
+    lib = P.load()
+    rs = np.array([0, 2, 4], np.int64)
+    out = __import__("ctypes").c_void_p()
+    assert lib.hx_plan_from_halos(2, rs.ctypes.data_as(P._lib.I64P), None, rs.ctypes.data_as(P._lib.I64P), None,
+                                  None, __import__("ctypes").byref(out)) == P.HX_ERR_ARG   # null info
 
 
 def test_product_path_has_no_cpu_fallback(monkeypatch, tmp_path):

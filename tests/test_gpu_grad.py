@@ -236,9 +236,9 @@ def test_world_backward_plain_launch_equals_graph(variant, sim):
     assert bits_equal(g_graph, OM.exchange_adjoint_reference(halos, gy, n))
 
 
-def staged_exchange(rs, rp, cols, ppn, variant, ncols, dtype, sim=True):
+def staged_exchange(rs, rp, cols, ppn, variant, ncols, dtype, sim=True, node_map="block"):
     from paper_2309_07337_amd.autograd import HaloExchange
-    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    plan = gpu_plan(rs, rp, cols, ppn, variant, node_map)
     H = sum(int(P.hx_plan_field(plan, r, "halo").size) for r in range(len(rs) - 1))
     return HaloExchange(plan, int(rs[-1]), H, ncols, dtype=dtype, sim_transfer=sim, staged_backward=True), plan
 

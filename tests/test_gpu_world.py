@@ -33,18 +33,19 @@ def run_world(plan, x, H, plain_launch=False, sched=None):
     return b, halo
 
 
-def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, seed=11, full_stages=True):
+def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, seed=11, full_stages=True,
+                               node_map="block", n_variants=None):
     import torch
     dtype = torch.float64 if dtype_name == "f64" else torch.float32
     halos = OP.all_halos(rp, cols, rs)
-    D = OP.Decomposition(halos, rs, ppn)
+    D = OP.Decomposition(halos, rs, ppn, node_map)
     R = len(rs) - 1
     n = int(rs[-1])
     xh = uniform_pm1(seed, n * ncols).reshape(n, ncols)
     if dtype_name == "f32":
         xh = xh.astype(np.float32)
     x = dev(xh)
-    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    plan = gpu_plan(rs, rp, cols, ppn, variant, node_map)
     H = sum(h.size for h in halos)
     variants = [(False, None), (True, None), (False, dict(push_pack=1, unroll=4, tile_rows=77)),
                 (False, dict(push_pack=2, unroll=2, nontemporal=1)),
@@ -64,6 +65,7 @@ def check_world_against_oracle(rs, rp, cols, ppn, variant, ncols, dtype_name, se
                                 unroll=4, nontemporal=1)),
                 (False, dict(push_pack=2, lds_window=1, pair_rows=1, block_threads=256, blocks_per_cu=1,
                              tile_rows=7, unroll=1))]
+    variants = variants[:n_variants]
     ref = np.concatenate([xh[h] for h in halos]) if H else np.zeros((0, ncols), xh.dtype)
     out = OM.forward_all([D.plan(r, variant) for r in range(R)], xh, rs) if full_stages else None
     for plain_launch, sched in variants:
