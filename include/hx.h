@@ -314,7 +314,9 @@ int hx_req_arena(hx_req* req, int which, void** dev_ptr, int64_t* rows);
  * -0.0 stays -0.0), rows never packed get +0.0.  g_send device [E1, ncols],
  * g_x device [n_local, ncols]; bound persistently. */
 int hx_req_bind_grad(hx_req* req, const void* g_send, void* g_x);
-/* Partition-ready pack (the GPU half of partitioned, early-bird sends):
+/* Partition-ready pack: the GPU half of partitioned, early-bird sends
+ * (Sec. 2.3: portions of a buffer marked ready may leave before the whole
+ * message is complete; here each stage-1 message is one partition).
  * hx_req_enable_ready allocates one 64-bit completion counter per stage-1
  * message (in the order of the request's send list), zeroed, owned by the
  * request, and returns their device address.  From then on the pack runs in
