@@ -238,6 +238,10 @@ int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local,
  *   messages plus one deduplicated message per remote node, sent to the
  *   partner there), stage-2 (redistribution) lists,
  *   the unpack map into the halo, and the transpose of the pack map.
+ * hx_plan_from_csr marks one bit per (rank, column) to find the halos; it
+ * does so for a group of ranks at a time, holding at most 1 GiB of bitmaps
+ * (the environment variable HX_PLAN_BITMAP_BYTES, read at each call, sets
+ * another budget; a group has at least one rank).
  * info (host, read during the call): variant, ranks per node and node map.
  * The plan owns its device arrays; inputs are read during the call only.
  * The call synchronises stream before returning.  Errors: HX_ERR_ARG (null

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <memory>
 #include <numeric>
 #include <vector>
@@ -253,9 +254,13 @@ __global__ void k_sum_i32(const int32_t* __restrict__ a, int64_t n, unsigned lon
 // Halo discovery
 // ---------------------------------------------------------------------------
 // Marks every off-rank column of each row in its rank's bitmap.
-__global__ void k_mark_csr(const int64_t* __restrict__ rs, int R, int64_t n, const int64_t* __restrict__ row_ptr,
-                           const int32_t* __restrict__ cols, uint32_t* B, int64_t W, int* err) {
-  GRID_STRIDE(i, n) {
+// Rows [i0, i0 + rows) belong to ranks r0, r0 + 1, ...; their bitmaps are the
+// rows of B counted from r0.
+__global__ void k_mark_csr(const int64_t* __restrict__ rs, int R, int64_t n, int64_t i0, int64_t rows, int r0,
+                           const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ cols, uint32_t* B,
+                           int64_t W, int* err) {
+  GRID_STRIDE(k, rows) {
+    const int64_t i = i0 + k;
     const int r = upper_rank(rs, R, i);
     const int64_t lo = rs[r], hi = rs[r + 1];
     const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
@@ -263,7 +268,7 @@ __global__ void k_mark_csr(const int64_t* __restrict__ rs, int R, int64_t n, con
       atomicOr(err, 8);
       continue;
     }
-    uint32_t* Br = B + (size_t)r * W;
+    uint32_t* Br = B + (size_t)(r - r0) * W;
     for (int64_t e = e0; e < e1; ++e) {
       const int64_t c = cols[e];
       if (c < 0 || c >= n) {
@@ -1085,36 +1090,64 @@ extern "C" int hx_plan_from_csr(int nranks, const int64_t* row_starts, const hx_
   std::unique_ptr<hx_plan> p;
   HX_TRY(plan_alloc(nranks, row_starts, info, &p));
   const int64_t W = (n + 31) / 32;
-  const double bitmap_gb = (double)nranks * W * 4 / 1e9;
-  if (bitmap_gb > 64.0) return fail(HX_ERR_UNSUPPORTED, "halo bitmaps would need %.1f GB", bitmap_gb);
+  // Halo discovery marks one bit per (rank, column).  The bitmaps of a group
+  // of ranks are built, counted and compacted before the next group, so the
+  // bitmap memory stays within a budget whatever the rank count.
+  int64_t budget = (int64_t)1 << 30;
+  if (const char* e = std::getenv("HX_PLAN_BITMAP_BYTES")) budget = std::max<int64_t>(1, std::atoll(e));
+  const int64_t group = std::max<int64_t>(1, std::min<int64_t>(nranks, budget / std::max<int64_t>(W * 4, 1)));
   DevMem B, err, cnt;
-  HX_TRY(zeros(&B, (size_t)nranks * W * 4, s));
+  HX_TRY(B.alloc((size_t)std::max<int64_t>(group * W * 4, 4)));
   HX_TRY(zeros(&err, 4, s));
-  if (n > 0) {
-    hipLaunchKernelGGL(k_mark_csr, dim3(blocks_for(n)), dim3(TB), 0, s, p->row_starts_d.as<int64_t>(), nranks, n,
-                       row_ptr, cols, B.as<uint32_t>(), W, err.as<int>());
+  HX_TRY(cnt.alloc((size_t)group * 8));
+  std::vector<int64_t> hoff(1, 0);
+  std::vector<DevMem> parts;
+  for (int r0 = 0; r0 < nranks; r0 += (int)group) {
+    const int g = (int)std::min<int64_t>(group, nranks - r0);
+    const int64_t i0 = row_starts[r0], rows = row_starts[r0 + g] - i0;
+    if (W > 0) HX_HIP(hipMemsetAsync(B.p, 0, (size_t)g * W * 4, s));
+    if (rows > 0) {
+      hipLaunchKernelGGL(k_mark_csr, dim3(blocks_for(rows)), dim3(TB), 0, s, p->row_starts_d.as<int64_t>(), nranks,
+                         n, i0, rows, r0, row_ptr, cols, B.as<uint32_t>(), W, err.as<int>());
+      HX_HIP(hipGetLastError());
+    }
+    HX_HIP(hipStreamSynchronize(s));
+    HX_TRY(check_err(err, "csr"));
+    hipLaunchKernelGGL(k_popc_rows, dim3(g), dim3(TB), 0, s, B.as<uint32_t>(), W, cnt.as<int64_t>());
     HX_HIP(hipGetLastError());
+    HX_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> hc;
+    HX_TRY(to_host64(cnt, g, &hc));
+    std::vector<int64_t> off = prefix(hc);
+    if (hoff.back() + off.back() >= INT32_MAX) return fail(HX_ERR_UNSUPPORTED, "total halo beyond 2^31 entries");
+    for (int k = 0; k < g; ++k) hoff.push_back(hoff.back() + hc[k]);
+    parts.emplace_back();
+    if (off.back() > 0) {
+      DevMem off_d;
+      HX_TRY(upload_vec(off_d, off));
+      HX_TRY(parts.back().alloc((size_t)off.back() * 4));
+      hipLaunchKernelGGL(k_compact_bits, dim3(g), dim3(TB), 0, s, B.as<uint32_t>(), W, off_d.as<int64_t>(),
+                         parts.back().as<int32_t>());
+      HX_HIP(hipGetLastError());
+      HX_HIP(hipStreamSynchronize(s));
+    }
   }
-  HX_HIP(hipStreamSynchronize(s));
-  HX_TRY(check_err(err, "csr"));
-  HX_TRY(cnt.alloc((size_t)nranks * 8));
-  hipLaunchKernelGGL(k_popc_rows, dim3(nranks), dim3(TB), 0, s, B.as<uint32_t>(), W, cnt.as<int64_t>());
-  HX_HIP(hipGetLastError());
-  HX_HIP(hipStreamSynchronize(s));
-  std::vector<int64_t> hc;
-  HX_TRY(to_host64(cnt, nranks, &hc));
-  std::vector<int64_t> hoff = prefix(hc);
-  if (hoff.back() >= INT32_MAX) return fail(HX_ERR_UNSUPPORTED, "total halo beyond 2^31 entries");
-  DevMem hoff_d, hcol;
-  HX_TRY(upload_vec(hoff_d, hoff));
-  HX_TRY(hcol.alloc((size_t)hoff.back() * 4));
-  if (hoff.back() > 0) {
-    hipLaunchKernelGGL(k_compact_bits, dim3(nranks), dim3(TB), 0, s, B.as<uint32_t>(), W, hoff_d.as<int64_t>(),
-                       hcol.as<int32_t>());
-    HX_HIP(hipGetLastError());
-  }
-  HX_HIP(hipStreamSynchronize(s));
   B.release();
+  DevMem hcol;
+  if (parts.size() == 1) {
+    hcol = std::move(parts[0]);
+  } else {
+    HX_TRY(hcol.alloc((size_t)hoff.back() * 4));
+    int64_t at = 0;
+    for (DevMem& d : parts) {
+      const int64_t len = (int64_t)(d.bytes / 4);
+      if (len > 0)
+        HX_HIP(hipMemcpyAsync(hcol.as<int32_t>() + at, d.p, (size_t)len * 4, hipMemcpyDeviceToDevice, s));
+      at += len;
+    }
+    HX_HIP(hipStreamSynchronize(s));
+    parts.clear();
+  }
   HX_TRY(build_from_halos(p.get(), hcol, hoff, 0, s));
   *out = p.release();
   return HX_SUCCESS;

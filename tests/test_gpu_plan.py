@@ -136,3 +136,45 @@ def test_degenerate_decompositions():
                 plan = gpu_plan(rs, rp, cols, ppn, variant)
                 for r in range(R):
                     assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"n{n} R{R} ppn{ppn} r{r}")
+
+
+@pytest.fixture
+def bitmap_budget(monkeypatch):
+    """Sets the halo-discovery bitmap budget (bytes) for the calls of a test."""
+    def set_budget(nbytes):
+        monkeypatch.setenv("HX_PLAN_BITMAP_BYTES", str(int(nbytes)))
+    return set_budget
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_halo_discovery_one_rank_at_a_time(case, bitmap_budget):
+    """A bitmap budget below two ranks' bitmaps: every rank's halo is
+    discovered alone, and the plans still equal the oracle's."""
+    need_gpu()
+    n, R, mx, pf, seed, uneven, ppn = case
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    bitmap_budget(1)
+    for variant in ("plain", "locality"):
+        say("plan one rank per bitmap group", case, variant)
+        plan = gpu_plan(rs, rp, cols, ppn, variant)
+        for r in range(R):
+            assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"{variant} rank {r}")
+
+
+def test_halo_discovery_in_groups_random_rows(bitmap_budget):
+    """The 2^22-row matrix (2 GiB of bitmaps for 4096 ranks) discovered 128
+    ranks at a time (64 MiB): every halo equals the oracle's, sampled ranks'
+    full plans too."""
+    need_gpu()
+    rs, rp, cols = cached_random_rows()
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, 128)
+    bitmap_budget(64 << 20)
+    say("plan random_rows in bitmap groups")
+    plan = gpu_plan(rs, rp, cols, 128, "locality")
+    for r in range(4096):
+        assert np.array_equal(P.hx_plan_field(plan, r, "halo"), halos[r]), r
+    for r in (0, 127, 128, 1511, 4095):
+        assert_plan_equal(plan_rank(plan, r), D.plan(r, "locality"), f"rank {r}")
