@@ -80,13 +80,15 @@ typedef enum { HX_PLAIN = 0, HX_LOCALITY_2STEP = 1, HX_LOCALITY_3STEP = 2 } hx_v
 typedef enum { HX_NODES_BLOCK = 0, HX_NODES_CYCLIC = 1 } hx_node_map;
 
 /* Options of a plan (the info argument of a persistent init, Listing 4):
- * variant; ppn >= 1 ranks per node (ignored by HX_PLAIN); node_map (the
- * 3-step variant needs HX_NODES_BLOCK, since its aggregator packs its node's
- * rows as one contiguous range; HX_ERR_UNSUPPORTED otherwise). */
+ * variant (an hx_variant); ppn >= 1 ranks per node (ignored by HX_PLAIN);
+ * node_map (an hx_node_map; the 3-step variant needs HX_NODES_BLOCK, since
+ * its aggregator packs its node's rows as one contiguous range,
+ * HX_ERR_UNSUPPORTED otherwise).  The fields are plain ints so that any
+ * value a caller stores is checked (HX_ERR_ARG) rather than undefined. */
 typedef struct {
-  hx_variant variant;
+  int variant;
   int ppn;
-  hx_node_map node_map;
+  int node_map;
 } hx_info;
 
 typedef struct hx_topo hx_topo;
@@ -285,6 +287,17 @@ typedef enum {
 int hx_plan_field_size(const hx_plan* plan, int rank, hx_field field, int64_t* count);
 /* Copies a field to host memory dst (capacity given by hx_plan_field_size). */
 int hx_plan_field_copy(const hx_plan* plan, int rank, hx_field field, int32_t* dst);
+/* A field of every rank at once (host memory): offsets [nranks+1] (may be
+ * NULL) receives where each rank's array starts in the concatenation in rank
+ * order, dst (capacity offsets[nranks] elements; may be NULL) the
+ * concatenation.  Synchronous. */
+int hx_plan_field_all(const hx_plan* plan, hx_field field, int64_t* offsets, int32_t* dst);
+/* What a plan was built from: its rank count, rows n, info, and (row_starts
+ * non-NULL, capacity nranks+1) its row starts.  Any output may be NULL.
+ * With the halo field this is all a plan needs to be built again
+ * (hx_plan_from_halos gives the same arrays: plan building is deterministic),
+ * which is how a plan is saved and restored. */
+int hx_plan_describe(const hx_plan* plan, int* nranks, int64_t* n, hx_info* info, int64_t* row_starts);
 
 /* Persistent request for one rank of a plan (its arrays stay on the device).
  * x_local device [n_local, ncols]; halo device [H, ncols]. */

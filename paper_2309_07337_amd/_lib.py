@@ -39,7 +39,7 @@ EXPORTED = (
     "hx_error_string", "hx_last_hip_error", "hx_last_error_message", "hx_version", "hx_set_allocator",
     "hx_topo_create", "hx_topo_free", "hx_neighbor_alltoallv_init",
     "hx_plan_from_csr", "hx_plan_from_halos", "hx_plan_free", "hx_plan_field_size",
-    "hx_plan_field_copy", "hx_req_from_plan", "hx_start", "hx_wait", "hx_req_arena",
+    "hx_plan_field_copy", "hx_plan_field_all", "hx_plan_describe", "hx_req_from_plan", "hx_start", "hx_wait", "hx_req_arena",
     "hx_req_bind_grad", "hx_req_enable_ready", "hx_backward", "hx_backward_noalloc", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
     "hx_batch_start", "hx_batch_wait", "hx_batch_start_plain", "hx_batch_wait_plain",
     "hx_batch_bind_grad", "hx_batch_backward", "hx_batch_backward_plain", "hx_batch_tune",
@@ -99,6 +99,8 @@ def load() -> C.CDLL:
         "hx_plan_free": (C.c_int, [PP]),
         "hx_plan_field_size": (C.c_int, [VP, C.c_int, C.c_int, I64P]),
         "hx_plan_field_copy": (C.c_int, [VP, C.c_int, C.c_int, I32P]),
+        "hx_plan_field_all": (C.c_int, [VP, C.c_int, I64P, I32P]),
+        "hx_plan_describe": (C.c_int, [VP, C.POINTER(C.c_int), I64P, C.POINTER(hx_info), I64P]),
         "hx_req_from_plan": (C.c_int, [VP, C.c_int, VP, VP, C.c_int, C.c_int, PP]),
         "hx_start": (C.c_int, [VP, VP]),
         "hx_wait": (C.c_int, [VP, VP]),
@@ -352,6 +354,27 @@ def hx_plan_field(plan: Plan, rank: int, field: str) -> np.ndarray:
     out = np.empty(n.value, np.int32)
     _check(load().hx_plan_field_copy(plan.ptr, rank, fid, _p32(out)))
     return out
+
+
+def hx_plan_field_all(plan: Plan, field: str):
+    """(offsets [nranks+1], concatenation of every rank's array) of one field."""
+    fid = FIELD_ID[field]
+    R = hx_plan_describe(plan)["nranks"]
+    off = np.empty(R + 1, np.int64)
+    _check(load().hx_plan_field_all(plan.ptr, fid, _p64(off), None))
+    out = np.empty(int(off[-1]), np.int32)
+    _check(load().hx_plan_field_all(plan.ptr, fid, None, _p32(out)))
+    return off, out
+
+
+def hx_plan_describe(plan: Plan) -> dict:
+    """nranks, n, variant, ppn, node_map ("block" / "cyclic") and row_starts of a plan."""
+    R, n, info = C.c_int(), C.c_int64(), hx_info()
+    _check(load().hx_plan_describe(plan.ptr, C.byref(R), C.byref(n), C.byref(info), None))
+    rs = np.empty(R.value + 1, np.int64)
+    _check(load().hx_plan_describe(plan.ptr, None, None, None, _p64(rs)))
+    nm = {v: k for k, v in NODE_MAPS.items()}[info.node_map]
+    return dict(nranks=R.value, n=n.value, variant=info.variant, ppn=info.ppn, node_map=nm, row_starts=rs)
 
 
 def hx_req_from_plan(plan: Plan, rank: int, x_local, halo) -> Req:

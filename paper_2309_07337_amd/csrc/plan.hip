@@ -972,7 +972,7 @@ int plan_common_checks(int nranks, const int64_t* row_starts, const hx_info* inf
   if (!info) return fail(HX_ERR_ARG, "null info");
   if (nranks <= 0 || !row_starts) return fail(HX_ERR_ARG, "bad nranks / row_starts");
   if (nranks > HX_PLAN_MAX_RANKS) return fail(HX_ERR_UNSUPPORTED, "more than %d ranks", HX_PLAN_MAX_RANKS);
-  const hx_variant variant = info->variant;
+  const int variant = info->variant;
   if (variant != HX_PLAIN && variant != HX_LOCALITY_2STEP && variant != HX_LOCALITY_3STEP)
     return fail(HX_ERR_ARG, "bad variant");
   if (info->ppn < 1) return fail(HX_ERR_ARG, "ppn must be >= 1");
@@ -1187,6 +1187,28 @@ extern "C" int hx_plan_field_size(const hx_plan* p, int rank, hx_field f, int64_
   if (!p || !count) return fail(HX_ERR_ARG, "null argument");
   if (rank < 0 || rank >= p->R || (int)f < 0 || f >= HX_F_COUNT) return fail(HX_ERR_RANGE, "bad rank or field");
   *count = p->size(f, rank);
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_plan_describe(const hx_plan* p, int* nranks, int64_t* n, hx_info* info, int64_t* row_starts) {
+  if (!p) return fail(HX_ERR_ARG, "null plan");
+  if (nranks) *nranks = p->R;
+  if (n) *n = p->n;
+  if (info) {
+    info->variant = p->variant;
+    info->ppn = p->ppn;
+    info->node_map = p->node_map;
+  }
+  if (row_starts) std::copy(p->row_starts.begin(), p->row_starts.end(), row_starts);
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_plan_field_all(const hx_plan* p, hx_field f, int64_t* offsets, int32_t* dst) {
+  if (!p) return fail(HX_ERR_ARG, "null plan");
+  if ((int)f < 0 || f >= HX_F_COUNT) return fail(HX_ERR_RANGE, "bad field");
+  if (offsets) std::copy(p->off[f].begin(), p->off[f].end(), offsets);
+  const int64_t c = p->tot(f);
+  if (dst && c > 0) HX_HIP(hipMemcpy(dst, p->d[f].p, (size_t)c * 4, hipMemcpyDeviceToHost));
   return HX_SUCCESS;
 }
 

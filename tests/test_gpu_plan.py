@@ -178,3 +178,31 @@ def test_halo_discovery_in_groups_random_rows(bitmap_budget):
         assert np.array_equal(P.hx_plan_field(plan, r, "halo"), halos[r]), r
     for r in (0, 127, 128, 1511, 4095):
         assert_plan_equal(plan_rank(plan, r), D.plan(r, "locality"), f"rank {r}")
+
+
+@pytest.mark.parametrize("variant,node_map", [("plain", "block"), ("locality", "cyclic"), ("locality3", "block")])
+def test_plan_save_and_restore(tmp_path, variant, node_map):
+    """A saved plan (27-point grid, 512 ranks) is rebuilt from its halos with
+    every field equal, and its description round-trips; a tampered file is
+    refused."""
+    need_gpu()
+    from paper_2309_07337_amd.planio import load_plan, save_plan
+    rs, rp, cols = cached_grid3d()
+    plan = gpu_plan(rs, rp, cols, 64, variant, node_map)
+    d = P.hx_plan_describe(plan)
+    assert d["nranks"] == 512 and d["n"] == 128 ** 3 and d["ppn"] == 64 and d["node_map"] == node_map
+    assert d["variant"] == variant_id(variant) and np.array_equal(d["row_starts"], rs)
+    off, h = P.hx_plan_field_all(plan, "halo")
+    assert np.array_equal(h[off[219]:off[220]], P.hx_plan_field(plan, 219, "halo"))
+    path = tmp_path / "plan.npz"
+    say("plan save/restore", variant, node_map)
+    save_plan(plan, path)
+    back = load_plan(path)
+    for r in (0, 219, 511):
+        assert_plan_equal(plan_rank(back, r), plan_rank(plan, r), f"rank {r}")
+    z = dict(np.load(path))
+    z["unpack_src"] = z["unpack_src"].copy()
+    z["unpack_src"][0] ^= 1
+    np.savez(tmp_path / "bad.npz", **z)
+    with pytest.raises(ValueError):
+        load_plan(tmp_path / "bad.npz")
