@@ -95,6 +95,7 @@ typedef struct hx_topo hx_topo;
 typedef struct hx_plan hx_plan;
 typedef struct hx_req hx_req;
 typedef struct hx_batch hx_batch;
+typedef struct hx_comm hx_comm;
 
 /* Launch schedule of the gather / segmented-sum kernels.  A zero field means
  * "library default".  per_neighbor = 1 splits each message into its own job
@@ -218,6 +219,45 @@ int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local,
                                const int* sendcounts, const int* sdispls, const int* send_idx,
                                void* halo, const int* recvcounts, const int* rdispls,
                                hx_dtype dtype, int ncols, const hx_topo* topo, hx_req** out);
+
+/* ---------------------------------------------------------------------------
+ * Per-rank locality-aware init -- Sec. 2.2, last paragraph (the extension
+ * takes, beside the neighbor lists, the global indices of all values sent
+ * and received).  Deduplicating over a node needs what every rank of the
+ * node receives, so the init is collective over a communicator; one process
+ * plays every rank of a simulated one:
+ *
+ * hx_comm_create: nranks ranks owning rows [row_starts[r], row_starts[r+1])
+ *   (host [nranks+1], copied), info (host, copied; variant HX_PLAIN or
+ *   HX_LOCALITY_2STEP, else HX_ERR_UNSUPPORTED), stream: where the plan is
+ *   built when the set completes.
+ * hx_neighbor_locality_alltoallv_init: rank topo->rank joins.  Arguments as
+ *   for hx_neighbor_alltoallv_init (displacements NULL or the prefix sums),
+ *   with global indices instead of local rows: global_sindices host
+ *   [sum(sendcounts)] int64, each owned by this rank; global_rindices host
+ *   [sum(recvcounts)] int64, the message from recv_procs[i] holding indices
+ *   owned by that rank, distinct over the whole receive list, in any order
+ *   (halo row u receives global index global_rindices[u]).  n_local must be
+ *   the rank's row count.  Lists are copied.  Until every rank has joined
+ *   the returned request is pending: every call on it but hx_req_free
+ *   returns HX_ERR_STATE.  The call that completes the set checks that what
+ *   q sends to s is, element for element, what s receives from q, builds the
+ *   plan on the GPU from the receive indices (hx_plan_from_halos) and fills
+ *   every joined request; its Start/Wait then run the plan's stages and the
+ *   unpack writes each halo row in the caller's receive order.  Errors of the
+ *   completing call (HX_ERR_ARG for lists that do not match) are returned by
+ *   it, without a request; the set's other requests then stay pending.
+ *   HX_ERR_STATE for a rank that joins twice or a set that is over.
+ * hx_comm_free: may be called at any time; requests of an incomplete set
+ *   stay pending, completed requests are independent of the communicator.
+ * ------------------------------------------------------------------------- */
+int hx_comm_create(int nranks, const int64_t* row_starts, const hx_info* info, void* stream, hx_comm** out);
+int hx_neighbor_locality_alltoallv_init(const void* x_local, int64_t n_local, const int* sendcounts,
+                                        const int* sdispls, const int64_t* global_sindices, void* halo,
+                                        const int* recvcounts, const int* rdispls,
+                                        const int64_t* global_rindices, hx_dtype dtype, int ncols,
+                                        const hx_topo* topo, hx_comm* comm, hx_req** out);
+int hx_comm_free(hx_comm** comm);
 
 /* ---------------------------------------------------------------------------
  * Plans of a whole decomposition, built on the GPU (all setup at init,

@@ -38,6 +38,7 @@ FIELD_ID = {k: i for i, k in enumerate(FIELDS)}
 EXPORTED = (
     "hx_error_string", "hx_last_hip_error", "hx_last_error_message", "hx_version", "hx_set_allocator",
     "hx_topo_create", "hx_topo_free", "hx_neighbor_alltoallv_init",
+    "hx_comm_create", "hx_comm_free", "hx_neighbor_locality_alltoallv_init",
     "hx_plan_from_csr", "hx_plan_from_halos", "hx_plan_free", "hx_plan_field_size",
     "hx_plan_field_copy", "hx_plan_field_all", "hx_plan_describe", "hx_req_from_plan", "hx_start", "hx_wait", "hx_req_arena",
     "hx_req_bind_grad", "hx_req_enable_ready", "hx_backward", "hx_backward_noalloc", "hx_req_free", "hx_batch_init", "hx_batch_from_plan",
@@ -94,6 +95,10 @@ def load() -> C.CDLL:
         "hx_topo_free": (C.c_int, [PP]),
         "hx_neighbor_alltoallv_init": (C.c_int, [VP, C.c_int64, I32P, I32P, I32P, VP, I32P, I32P, C.c_int,
                                                  C.c_int, VP, PP]),
+        "hx_comm_create": (C.c_int, [C.c_int, I64P, C.POINTER(hx_info), VP, PP]),
+        "hx_comm_free": (C.c_int, [PP]),
+        "hx_neighbor_locality_alltoallv_init": (C.c_int, [VP, C.c_int64, I32P, I32P, I64P, VP, I32P, I32P, I64P,
+                                                          C.c_int, C.c_int, VP, VP, PP]),
         "hx_plan_from_csr": (C.c_int, [C.c_int, I64P, C.POINTER(hx_info), VP, VP, VP, PP]),
         "hx_plan_from_halos": (C.c_int, [C.c_int, I64P, C.POINTER(hx_info), I64P, VP, VP, PP]),
         "hx_plan_free": (C.c_int, [PP]),
@@ -286,6 +291,10 @@ class Batch(_Handle):
     _free_name = "hx_batch_free"
 
 
+class Comm(_Handle):
+    _free_name = "hx_comm_free"
+
+
 # ---------------------------------------------------------------------------
 # Entry points (same names as the C ABI)
 # ---------------------------------------------------------------------------
@@ -322,6 +331,27 @@ def hx_neighbor_alltoallv_init(x_local, sendcounts, sdispls, send_idx, halo, rec
 def _info(ppn: int, variant: int, node_map) -> hx_info:
     nm = NODE_MAPS[node_map] if isinstance(node_map, str) else int(node_map)
     return hx_info(int(variant), int(ppn), nm)
+
+
+def hx_comm_create(nranks: int, row_starts, ppn: int, variant: int, node_map="block", stream=None) -> Comm:
+    """A simulated communicator for the collective per-rank locality-aware init."""
+    rs = _i64(row_starts)
+    info = _info(ppn, variant, node_map)
+    out = C.c_void_p()
+    _check(load().hx_comm_create(nranks, _p64(rs), C.byref(info), _stream(stream), C.byref(out)))
+    return Comm(out)
+
+
+def hx_neighbor_locality_alltoallv_init(x_local, sendcounts, sdispls, global_sindices, halo, recvcounts, rdispls,
+                                        global_rindices, topo: Topo, comm: Comm) -> Req:
+    """One rank joins the collective init (pending until every rank has joined)."""
+    sc, sd, rc, rd = _i32(sendcounts), _i32(sdispls), _i32(recvcounts), _i32(rdispls)
+    gs, gr = _i64(global_sindices), _i64(global_rindices)
+    out = C.c_void_p()
+    _check(load().hx_neighbor_locality_alltoallv_init(
+        _dptr(x_local), int(x_local.shape[0]), _p32(sc), _p32(sd), _p64(gs), _dptr(halo), _p32(rc), _p32(rd),
+        _p64(gr), _dtype_of(x_local), _ncols(x_local), topo.ptr, comm.ptr, C.byref(out)))
+    return Req(out, keep=(x_local, halo, topo, comm))
 
 
 def hx_plan_from_csr(nranks: int, row_starts, ppn: int, variant: int, row_ptr, cols, stream=None,

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhx.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["move_gather.hip", "move_segsum.hip", "move_scatter.hip", "move.hip", "plan.hip", "world.hip", "noalloc.hip", "runtime.cpp"]
+SOURCES = ["move_gather.hip", "move_segsum.hip", "move_scatter.hip", "move.hip", "plan.hip", "world.hip", "noalloc.hip", "runtime.cpp", "comm.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

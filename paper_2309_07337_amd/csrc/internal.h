@@ -11,6 +11,13 @@
 namespace hx {
 enum Phase { PH_PACK = 0, PH_REDIST = 1, PH_UNPACK = 2, PH_BWD = 3 };
 }
+struct hx_comm;
+
+// A rank's neighbor topology (host copies of its lists).
+struct hx_topo {
+  int rank = 0, nranks = 0;
+  std::vector<int> recv_procs, send_procs;
+};
 
 // One rank's persistent request (rank-local arrays on the device).
 struct hx_req {
@@ -35,6 +42,29 @@ struct hx_req {
   bool tables_built = false;
   hx::LaunchTable lt[4];
   hx::DevMem ready;  // per stage-1 message completion counters (uint64), when enabled
+  // joined a collective locality-aware init that has not completed yet: the
+  // request has no arrays and every call but free refuses it
+  bool pending = false;
+  hx_comm* comm = nullptr;  // the communicator it joined (while pending)
+};
+
+// A simulated communicator for the collective locality-aware init: every
+// rank's lists are collected, and the call that completes the set builds
+// the plan and fills every joined request.
+struct hx_comm {
+  int R = 0;
+  std::vector<int64_t> row_starts;  // host [R+1]
+  hx_info info{};
+  hipStream_t stream = nullptr;
+  struct Slot {
+    bool joined = false;
+    hx_req* req = nullptr;  // while pending; nullptr once freed by its owner or completed
+    std::vector<int> rprocs, rcounts, sprocs, scounts;
+    std::vector<int64_t> rind, sind;  // global indices in the caller's order
+  };
+  std::vector<Slot> slot;
+  int joined = 0;
+  int state = 0;  // 0 collecting, 1 complete, < 0 failed with that code
 };
 
 // Plan of a whole decomposition: per-rank arrays stored flat on the device,
@@ -109,6 +139,11 @@ int req_jobs(const hx_req* r, int phase, const Sched& sc, std::vector<GatherJob>
 int build_phase_table(int phase, const Sched& sc, int dtype, int row_bytes, const std::vector<GatherJob>& g,
                       const std::vector<SegSumJob>& s, LaunchTable* t);
 void req_compute_bytes(hx_req* r);
+// Fills r (fresh, or pending) with rank `rank`'s arrays of plan p.
+int req_fill_from_plan(const hx_plan* p, int rank, const void* x_local, void* halo, int dtype, int ncols,
+                       hx_req* r);
+// HX_ERR_STATE for a request whose collective init has not completed.
+int req_usable(const hx_req* r);
 void batch_destroy_graphs(hx_batch* b);
 int batch_phase_jobs(const hx_batch* b, int phase, const Sched& sc, bool merged,
                      std::vector<std::vector<GatherJob>>* g, std::vector<std::vector<SegSumJob>>* s);

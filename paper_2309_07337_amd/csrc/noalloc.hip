@@ -41,6 +41,7 @@ int scratch_address(void** out) {
 
 extern "C" int hx_backward_noalloc(hx_req* r, const void* g_send, void* g_x, void* stream) {
   if (!r) return hx::fail(HX_ERR_ARG, "null request");
+  HX_TRY(hx::req_usable(r));
   if (r->E1 > 0 && !g_send) return hx::fail(HX_ERR_ARG, "null g_send");
   if (r->n_local > 0 && !g_x) return hx::fail(HX_ERR_ARG, "null g_x");
   if (r->n_local == 0) return HX_SUCCESS;

@@ -226,11 +226,6 @@ using namespace hx;
 // ===========================================================================
 // Topology
 // ===========================================================================
-struct hx_topo {
-  int rank = 0, nranks = 0;
-  std::vector<int> recv_procs, send_procs;
-};
-
 static int check_procs(int rank, int nranks, int n, const int* procs, const char* what) {
   if (n < 0) return fail(HX_ERR_ARG, "%s: negative neighbor count", what);
   if (n > 0 && !procs) return fail(HX_ERR_ARG, "%s: null neighbor list", what);
@@ -469,8 +464,14 @@ extern "C" int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local, 
   return HX_SUCCESS;
 }
 
+int hx::req_usable(const hx_req* r) {
+  if (r->pending) return fail(HX_ERR_STATE, "the collective init this request joined has not completed");
+  return HX_SUCCESS;
+}
+
 extern "C" int hx_start(hx_req* r, void* stream) {
   if (!r) return fail(HX_ERR_ARG, "null request");
+  HX_TRY(req_usable(r));
   if (r->active) return fail(HX_ERR_STATE, "request already active");
   HX_TRY(build_req_tables(r));
   HX_TRY(launch_table(r->lt[PH_PACK], (hipStream_t)stream));
@@ -480,6 +481,7 @@ extern "C" int hx_start(hx_req* r, void* stream) {
 
 extern "C" int hx_wait(hx_req* r, void* stream) {
   if (!r) return fail(HX_ERR_ARG, "null request");
+  HX_TRY(req_usable(r));
   if (!r->active) return HX_SUCCESS;
   HX_TRY(build_req_tables(r));
   HX_TRY(launch_table(r->lt[PH_REDIST], (hipStream_t)stream));
@@ -490,6 +492,7 @@ extern "C" int hx_wait(hx_req* r, void* stream) {
 
 extern "C" int hx_req_arena(hx_req* r, int which, void** dev_ptr, int64_t* rows) {
   if (!r || !dev_ptr || !rows) return fail(HX_ERR_ARG, "null argument");
+  HX_TRY(req_usable(r));
   if (which == HX_ARENA_SEND) {
     *dev_ptr = r->send.p;
     *rows = r->E1 + r->E2;
@@ -504,6 +507,7 @@ extern "C" int hx_req_arena(hx_req* r, int which, void** dev_ptr, int64_t* rows)
 
 extern "C" int hx_req_enable_ready(hx_req* r, unsigned long long** dev_counters) {
   if (!r || !dev_counters) return fail(HX_ERR_ARG, "null argument");
+  HX_TRY(req_usable(r));
   if (r->active) return fail(HX_ERR_STATE, "request active");
   if (!r->ready.p) {
     const size_t n = std::max<size_t>(r->s1_counts.size(), 1);
@@ -517,6 +521,7 @@ extern "C" int hx_req_enable_ready(hx_req* r, unsigned long long** dev_counters)
 
 extern "C" int hx_req_bind_grad(hx_req* r, const void* g_send, void* g_x) {
   if (!r) return fail(HX_ERR_ARG, "null request");
+  HX_TRY(req_usable(r));
   if ((r->E1 > 0 && !g_send) || (r->n_local > 0 && !g_x)) return fail(HX_ERR_ARG, "null gradient buffer");
   r->g_send = static_cast<const char*>(g_send);
   r->g_x = static_cast<char*>(g_x);
@@ -533,12 +538,14 @@ extern "C" int hx_req_bind_grad(hx_req* r, const void* g_send, void* g_x) {
 
 extern "C" int hx_backward(hx_req* r, void* stream) {
   if (!r) return fail(HX_ERR_ARG, "null request");
+  HX_TRY(req_usable(r));
   if (!r->g_x && r->n_local > 0) return fail(HX_ERR_STATE, "no gradient buffers bound");
   return launch_table(r->lt[PH_BWD], (hipStream_t)stream);
 }
 
 extern "C" int hx_req_free(hx_req** r) {
   if (!r) return HX_SUCCESS;
+  if (*r && (*r)->comm) (*r)->comm->slot[(*r)->rank].req = nullptr;  // the collective forgets it
   delete *r;
   *r = nullptr;
   return HX_SUCCESS;
@@ -792,6 +799,7 @@ extern "C" int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, 
   if (n <= 0 || !reqs) return fail(HX_ERR_ARG, "empty batch");
   for (int i = 0; i < n; ++i) {
     if (!reqs[i]) return fail(HX_ERR_ARG, "null member %d", i);
+    HX_TRY(req_usable(reqs[i]));
     if (reqs[i]->dtype != reqs[0]->dtype || reqs[i]->ncols != reqs[0]->ncols)
       return fail(HX_ERR_ARG, "members differ in dtype or ncols");
   }

@@ -311,18 +311,14 @@ static int64_t distinct_count(const std::vector<int32_t>& v, int64_t domain) {
   return u;
 }
 
-extern "C" int hx_req_from_plan(const hx_plan* p, int rank, const void* x_local, void* halo, hx_dtype dtype,
-                                int ncols, hx_req** out) {
-  if (!out) return fail(HX_ERR_ARG, "null out");
-  *out = nullptr;
+int hx::req_fill_from_plan(const hx_plan* p, int rank, const void* x_local, void* halo, int dtype, int ncols,
+                           hx_req* r) {
   if (!p) return fail(HX_ERR_ARG, "null plan");
   if (rank < 0 || rank >= p->R) return fail(HX_ERR_RANGE, "rank out of range");
   if (dtype != HX_F32 && dtype != HX_F64) return fail(HX_ERR_ARG, "bad dtype");
   if (ncols <= 0) return fail(HX_ERR_ARG, "ncols must be positive");
   if (p->variant == HX_LOCALITY_3STEP)
     return fail(HX_ERR_UNSUPPORTED, "3-step plans pack node-mates' rows: use a whole-decomposition batch");
-  std::unique_ptr<hx_req> r(new (std::nothrow) hx_req);
-  if (!r) return fail(HX_ERR_NOMEM, "out of host memory");
   r->dtype = dtype;
   r->ncols = ncols;
   r->row_bytes = (size_t)ncols * dtype_bytes(dtype);
@@ -376,7 +372,17 @@ extern "C" int hx_req_from_plan(const hx_plan* p, int rank, const void* x_local,
   r->U_redist = distinct_count(s2, r->R1);
   HX_TRY(r->send.alloc((size_t)(r->E1 + r->E2) * r->row_bytes));
   HX_TRY(r->recv.alloc((size_t)(r->R1 + r->R2) * r->row_bytes));
-  req_compute_bytes(r.get());
+  req_compute_bytes(r);
+  return HX_SUCCESS;
+}
+
+extern "C" int hx_req_from_plan(const hx_plan* p, int rank, const void* x_local, void* halo, hx_dtype dtype,
+                                int ncols, hx_req** out) {
+  if (!out) return fail(HX_ERR_ARG, "null out");
+  *out = nullptr;
+  std::unique_ptr<hx_req> r(new (std::nothrow) hx_req);
+  if (!r) return fail(HX_ERR_NOMEM, "out of host memory");
+  HX_TRY(req_fill_from_plan(p, rank, x_local, halo, dtype, ncols, r.get()));
   *out = r.release();
   return HX_SUCCESS;
 }

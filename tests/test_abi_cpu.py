@@ -154,3 +154,46 @@ def test_allocator_failure_is_nomem_without_a_gpu():
         assert lib.hx_set_allocator(L._TORCH_ALLOC, L.FREE_FN(0), None) == P.HX_ERR_ARG
     finally:
         L.use_torch_allocator()
+
+
+def test_collective_locality_init_checks_on_host():
+    """The per-rank locality-aware init: a joined request is pending (every
+    call on it refuses), a rank cannot join twice, and a completing call
+    whose ranks' lists do not match fails before any device work, leaving
+    the set over."""
+    with pytest.raises(P.HXError) as e:
+        P.hx_comm_create(2, [0, 3, 6], 1, P.HX_LOCALITY_3STEP, stream=0)
+    assert e.value.code == P.HX_ERR_UNSUPPORTED
+    with pytest.raises(P.HXError) as e:
+        P.hx_comm_create(2, [0, 3, 6], 1, P.HX_LOCALITY_2STEP, node_map=5, stream=0)
+    assert e.value.code == P.HX_ERR_ARG
+    comm = P.hx_comm_create(2, [0, 3, 6], 1, P.HX_LOCALITY_2STEP, stream=0)
+    t0 = P.hx_topo_create(0, 2, [1], [1])
+    t1 = P.hx_topo_create(1, 2, [0], [0])
+    x, h = FakeTensor(3), FakeTensor(2)
+    r0 = P.hx_neighbor_locality_alltoallv_init(x, [1], None, [1], h, [2], None, [3, 4], t0, comm)
+    with pytest.raises(P.HXError) as e:
+        P.hx_start(r0, stream=0)
+    assert e.value.code == P.HX_ERR_STATE
+    with pytest.raises(P.HXError) as e:
+        P.hx_neighbor_locality_alltoallv_init(x, [1], None, [1], h, [2], None, [3, 4], t0, comm)
+    assert e.value.code == P.HX_ERR_STATE
+    # rank 1 sends [3, 4] (as rank 0 expects) but expects [0] where rank 0 sends [1]
+    x1, h1 = FakeTensor(3), FakeTensor(1)
+    with pytest.raises(P.HXError) as e:
+        P.hx_neighbor_locality_alltoallv_init(x1, [2], None, [3, 4], h1, [1], None, [0], t1, comm)
+    assert e.value.code == P.HX_ERR_ARG
+    with pytest.raises(P.HXError) as e:
+        P.hx_start(r0, stream=0)
+    assert e.value.code == P.HX_ERR_STATE
+    # an index the source does not own, and a wrong row count
+    comm2 = P.hx_comm_create(2, [0, 3, 6], 1, P.HX_PLAIN, stream=0)
+    with pytest.raises(P.HXError) as e:
+        P.hx_neighbor_locality_alltoallv_init(x, [1], None, [1], h, [2], None, [2, 4], t0, comm2)
+    assert e.value.code == P.HX_ERR_RANGE
+    with pytest.raises(P.HXError) as e:
+        P.hx_neighbor_locality_alltoallv_init(FakeTensor(4), [1], None, [1], h, [2], None, [3, 4], t0, comm2)
+    assert e.value.code == P.HX_ERR_ARG
+    r0.free()
+    comm.free()
+    comm2.free()
