@@ -11,7 +11,7 @@ import pytest
 import paper_2309_07337_amd as P
 from oracle import plan as OP
 from tests.conftest import cached_grid2d, cached_grid3d, cached_random_rows
-from tests.gpu_util import assert_plan_equal, dev, gpu_plan, need_gpu, plan_rank, say, variant_id
+from tests.gpu_util import assert_plan_equal, dev, gpu_plan, host, need_gpu, plan_rank, say, variant_id
 from tests.test_oracle_brute import CASES
 from workloads import random_small_csr
 
@@ -206,3 +206,35 @@ def test_plan_save_and_restore(tmp_path, variant, node_map):
     np.savez(tmp_path / "bad.npz", **z)
     with pytest.raises(ValueError):
         load_plan(tmp_path / "bad.npz")
+
+
+def test_plan_and_exchange_at_the_rank_cap():
+    """HX_PLAN_MAX_RANKS ranks (16384) of a 2^21-row random matrix (128 rows
+    per rank, 8 entries per row, 64 ranks per node): halo discovery in four
+    1 GiB bitmap groups, sampled ranks' full locality plans against the
+    oracle, every halo, and the exchange of all ranks equal to the direct
+    gather."""
+    need_gpu()
+    import torch
+    from tests.test_gpu_world import run_world
+    from workloads import equal_row_starts, random_rows, uniform_pm1
+    R = P.HX_PLAN_MAX_RANKS
+    n = 1 << 21
+    rp, cols = random_rows(n, 8, R, 77)
+    rs = equal_row_starts(n, R)
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, 64)
+    say("plan at the rank cap")
+    plan = gpu_plan(rs, rp, cols, 64, "locality")
+    off, h = P.hx_plan_field_all(plan, "halo")
+    assert np.array_equal(np.diff(off), [x.size for x in halos])
+    assert np.array_equal(h, np.concatenate(halos))
+    for r in (0, 63, 64, 8191, R - 1):
+        assert_plan_equal(plan_rank(plan, r), D.plan(r, "locality"), f"rank {r}")
+    say("exchange at the rank cap")
+    xh = uniform_pm1(78, n).reshape(n, 1)
+    b, halo = run_world(plan, dev(xh), int(off[-1]))
+    assert np.array_equal(host(halo), xh[h])
+    b.free()
+    del plan
+    torch.cuda.empty_cache()
