@@ -172,3 +172,68 @@ def test_partition_ready_counters(ncols):
         send = host(P.req_arena_view(req, P.HX_ARENA_SEND, ncols, torch.float64))
         assert bits_equal(send, OM.pack(host(x), lists["send_idx"]))
     bt.free()
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+def test_request_steps_replayed_from_a_captured_graph(variant):
+    """Start, Wait and the backward of one rank's request (built from a GPU
+    plan, 2 FP64 columns) recorded in a CUDA graph after one eager step, then
+    replayed four times with new vector, receive-arena and gradient values
+    written eagerly between the replays (and unrelated eager work): every
+    replay's send arena, halo and gradient equal the oracle's for that
+    replay's inputs."""
+    need_gpu()
+    import torch
+    from tests.gpu_util import gpu_plan
+    from tests.test_oracle_brute import CASES
+    from workloads import random_small_csr
+    n, R, mx, pf, seed, uneven, ppn = CASES[4]
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    plans = [D.plan(q, variant) for q in range(R)]
+    r = max(range(R), key=lambda q: halos[q].size)
+    C = 2
+    plan = gpu_plan(rs, rp, cols, ppn, variant)
+    nl = int(rs[r + 1] - rs[r])
+    x_local = torch.zeros(nl, C, dtype=torch.float64, device="cuda")
+    halo = torch.full((halos[r].size, C), float("nan"), dtype=torch.float64, device="cuda")
+    req = P.hx_req_from_plan(plan, r, x_local, halo)
+    recv = P.req_arena_view(req, P.HX_ARENA_RECV, C, torch.float64)
+    send = P.req_arena_view(req, P.HX_ARENA_SEND, C, torch.float64)
+    E1 = int(plans[r]["s1_idx"].size)
+    g_send = torch.zeros(E1, C, dtype=torch.float64, device="cuda")
+    g_x = torch.full_like(x_local, float("nan"))
+    P.hx_req_bind_grad(req, g_send, g_x)
+
+    def step():
+        P.hx_start(req)
+        P.hx_wait(req)
+        P.hx_backward(req)
+
+    step()                      # eager: builds the launch tables
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    other = torch.zeros(1 << 20, device="cuda")
+    for it in range(4):
+        xh = uniform_pm1(4000 + it, int(rs[-1]) * C).reshape(-1, C)
+        out = OM.forward_all(plans, xh, rs)
+        gh = uniform_pm1(5000 + it, E1 * C).reshape(E1, C)
+        x_local.copy_(dev(xh[rs[r]:rs[r + 1]]))
+        recv.copy_(dev(out["arena"][r]))
+        g_send.copy_(dev(gh))
+        halo.fill_(float("nan"))
+        g_x.fill_(float("nan"))
+        other.add_(1.0)          # unrelated eager work between replays
+        torch.cuda.synchronize()
+        say("captured request step, replay", variant, it)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert bits_equal(host(send), np.concatenate([out["send1"][r], out["send2"][r]])), it
+        assert bits_equal(host(halo), out["halo"][r]), it
+        want = OM.pack_transpose(gh, plans[r]["bt_ptr"], plans[r]["bt_perm"])
+        assert bits_equal(host(g_x), want), it
+    del graph
+    req.free()
