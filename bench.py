@@ -363,25 +363,25 @@ def time_cold(torch, P, batch, phases, flush, runs=20):
 
 def time_kernels(torch, P, batch, reps, phases):
     """Average duration of each phase's kernel, launched alone (the same
-    launch table the step replays) in step order, events between the
-    launches, so that each kernel meets the caches its predecessors left (as
-    in the step); `reps` rounds."""
+    launch table the step replays): per phase, `reps` launches back to back
+    between two HIP events on the launch stream, queued behind a bounded
+    spin kernel so that no host launch gap falls between them (as in a
+    profiler's kernel trace)."""
     P.hx_batch_wait(batch)
     for p in phases:
         P.hx_batch_launch_phase(batch, p)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(reps)]
-    # a bounded spin kernel first, so that every launch below is queued
-    # before the first one runs: the events then bracket the kernels alone,
-    # with no host launch gaps between them (as a profiler's kernel trace)
-    torch.cuda._sleep(20_000_000)
-    for i in range(reps):
-        ev[i][0].record()
-        for k, p in enumerate(phases):
+    out = {}
+    for p in phases:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(20_000_000)
+        e0.record()
+        for _ in range(reps):
             P.hx_batch_launch_phase(batch, p)
-            ev[i][k + 1].record()
-    torch.cuda.synchronize()
-    return {p: sum(e[k].elapsed_time(e[k + 1]) for e in ev) / reps for k, p in enumerate(phases)}
+        e1.record()
+        torch.cuda.synchronize()
+        out[p] = e0.elapsed_time(e1) / reps
+    return out
 
 
 NAMES = {0: "pack", 1: "redist", 2: "unpack", 3: "backward"}
@@ -416,7 +416,7 @@ def measure(name, S, args, torch, P, flush, plain=True):
         log(f"{name} plain: {plain_ms:.3f} ms/step; phases (ms) {json.dumps({k: round(v, 4) for k, v in pph.items()})}")
     step_bytes = sum(v for ph_id, v in nbytes.items() if ph_id != 3 or 3 in S["phases"])
     value = step_bytes / (ms * 1e-3) / 1e9
-    kms = time_kernels(torch, P, b, max(5, args.steps // 2), [p for p in (0, 1, 2, 3) if nbytes[p] > 0])
+    kms = time_kernels(torch, P, b, max(10, args.steps // 2), [p for p in (0, 1, 2, 3) if nbytes[p] > 0])
     log(f"{name} kernels alone (ms): {json.dumps({NAMES[p]: round(t, 4) for p, t in kms.items()})}")
     step_k = {p: t for p, t in kms.items() if p != 3 or 3 in S["phases"]}
     dom_p = max(step_k, key=lambda p: step_k[p])
