@@ -257,12 +257,18 @@ def setup_rank(args, torch, P, rank=1511):
     req = P.hx_req_from_plan(plan, rank, x, halo)
     recv = P.req_arena_view(req, P.HX_ARENA_RECV, 1, torch.float64)
     recv.copy_(torch.from_numpy(uniform_pm1(99, recv.shape[0]).reshape(-1, 1)).cuda())
+    # the backward of its pack: gradients of its stage-1 send slots summed into its rows
+    E1 = int(P.hx_plan_field(plan, rank, "s1_idx").size)
+    g_send = torch.from_numpy(uniform_pm1(101, E1).reshape(E1, 1)).cuda()
+    g_x = torch.empty_like(x)
+    P.hx_req_bind_grad(req, g_send, g_x)
     batch = P.hx_batch_init([req])
     tune(args, torch, P, batch, "rank1511")
     cfg = {"workload": f"random 2^22 x 32, locality 2-step plan, rank {rank} alone (its own request: "
                        f"{n_local} rows, halo {H}, 1 x FP64); warm, not an HBM figure",
            "rank": rank, "halo_rows": H, "recv_neighbors": int(P.hx_plan_field(plan, rank, "r1_procs").size)}
-    return dict(batch=batch, host=[], dtype="f64", cfg=cfg, phases=(0, 1, 2), keep=(plan, x, halo, req, recv))
+    return dict(batch=batch, host=[], dtype="f64", cfg=cfg, phases=(0, 1, 2),
+                keep=(plan, x, halo, req, recv, g_send, g_x))
 
 
 def tune(args, torch, P, batch, name):
