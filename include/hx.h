@@ -424,6 +424,9 @@ int hx_backward(hx_req* req, void* stream);
  * ------------------------------------------------------------------------- */
 #define HX_NOALLOC_SCRATCH_BYTES (1u << 20)
 int hx_backward_noalloc(hx_req* req, const void* g_send, void* g_x, void* stream);
+/* Frees a request (NULL or *req NULL: nothing).  HX_ERR_STATE, and nothing
+ * freed, while the request is active (Start without Wait) or a member of a
+ * batch that has not been freed. */
 int hx_req_free(hx_req** req);
 
 /* ---------------------------------------------------------------------------

@@ -264,7 +264,9 @@ class _Handle:
 
     def free(self):
         if self.ptr is not None and self.ptr.value:
-            getattr(load(), self._free_name)(C.byref(self.ptr))
+            rc = getattr(load(), self._free_name)(C.byref(self.ptr))
+            if rc != HX_SUCCESS:   # e.g. a request still active or held by a batch: kept
+                _check(rc)
         self.ptr = None
         self._keep = []
 

@@ -46,6 +46,7 @@ struct hx_req {
   // request has no arrays and every call but free refuses it
   bool pending = false;
   hx_comm* comm = nullptr;  // the communicator it joined (while pending)
+  int batch_refs = 0;       // batches holding it as a member (it may not be freed before them)
 };
 
 // A simulated communicator for the collective locality-aware init: every

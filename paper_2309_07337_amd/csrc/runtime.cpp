@@ -544,8 +544,11 @@ extern "C" int hx_backward(hx_req* r, void* stream) {
 }
 
 extern "C" int hx_req_free(hx_req** r) {
-  if (!r) return HX_SUCCESS;
-  if (*r && (*r)->comm) (*r)->comm->slot[(*r)->rank].req = nullptr;  // the collective forgets it
+  if (!r || !*r) return HX_SUCCESS;
+  if ((*r)->active) return fail(HX_ERR_STATE, "request active: wait before freeing it");
+  if ((*r)->batch_refs > 0) return fail(HX_ERR_STATE, "request is a member of %d batch(es): free them first",
+                                        (*r)->batch_refs);
+  if ((*r)->comm) (*r)->comm->slot[(*r)->rank].req = nullptr;  // the collective forgets it
   delete *r;
   *r = nullptr;
   return HX_SUCCESS;
@@ -816,6 +819,7 @@ extern "C" int hx_batch_init(hx_req* const* reqs, int n, const hx_sched* sched, 
   }
   HX_TRY(batch_init_scheds(b.get(), sched));
   HX_TRY(batch_prepare(b.get()));
+  for (hx_req* r : b->members) ++r->batch_refs;  // released by hx_batch_free
   *out = b.release();
   return HX_SUCCESS;
 }
@@ -1238,7 +1242,8 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
 }
 
 extern "C" int hx_batch_free(hx_batch** b) {
-  if (!b) return HX_SUCCESS;
+  if (!b || !*b) return HX_SUCCESS;
+  for (hx_req* r : (*b)->members) --r->batch_refs;
   delete *b;
   *b = nullptr;
   return HX_SUCCESS;

@@ -237,3 +237,26 @@ def test_request_steps_replayed_from_a_captured_graph(variant):
         assert bits_equal(host(g_x), want), it
     del graph
     req.free()
+
+
+def test_free_refused_while_active_or_batched():
+    """A request cannot be freed between Start and Wait, nor while a batch
+    holds it as a member; both are HX_ERR_STATE and leave it intact."""
+    need_gpu()
+    import torch
+    b, h, lists = small_plans()[0]
+    req, x, halo = make_req(lists, h, 2, torch.float64, 7)
+    P.hx_start(req)
+    with pytest.raises(P.HXError) as e:
+        req.free()
+    assert e.value.code == P.HX_ERR_STATE and req.ptr is not None
+    P.hx_wait(req)
+    batch = P.hx_batch_init([req, req])
+    with pytest.raises(P.HXError) as e:
+        req.free()
+    assert e.value.code == P.HX_ERR_STATE and req.ptr is not None
+    P.hx_batch_start(batch)     # the member is intact
+    P.hx_batch_wait(batch)
+    batch.free()
+    req.free()
+    assert req.ptr is None
