@@ -933,7 +933,8 @@ extern "C" int hx_batch_wait_plain(hx_batch* b, void* stream) {
 extern "C" int hx_batch_bind_grad(hx_batch* b, const void* g_in, void* g_out) {
   if (!b) return fail(HX_ERR_ARG, "null batch");
   if (!b->world) return fail(HX_ERR_ARG, "member batches use each member's hx_req_bind_grad");
-  if (!g_in || !g_out) return fail(HX_ERR_ARG, "null gradient buffer");
+  // (empty buffers may be null: a decomposition without halo entries, or without rows)
+  if ((!g_in && b->H_tot > 0) || (!g_out && b->n > 0)) return fail(HX_ERR_ARG, "null gradient buffer");
   b->g_in = static_cast<const char*>(g_in);
   b->g_out = static_cast<char*>(g_out);
   b->plain_built[PH_BWD] = false;

@@ -1,0 +1,92 @@
+"""Property-based GPU parity: hypothesis draws small decompositions (rows,
+ranks, entries per row, share of far entries, uneven splits, ranks per node,
+placement, plan variant, columns and dtype); for each, the GPU plan, every
+stage buffer of the world exchange and the staged backward equal the
+oracle's, bit for bit.  Derandomized, so every run takes the same
+examples."""
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import paper_2309_07337_amd as P
+from oracle import move as OM
+from oracle import plan as OP
+from tests.gpu_util import assert_plan_equal, bits_equal, dev, gpu_plan, host, need_gpu, plan_rank, say
+from tests.test_gpu_grad import staged_exchange
+from workloads import random_small_csr, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
+@given(n=st.integers(1, 300), R=st.integers(1, 24), mx=st.integers(1, 8), pf=st.floats(0.0, 1.0),
+       seed=st.integers(0, 10_000), uneven=st.booleans(), ppn=st.integers(1, 7),
+       placement=st.sampled_from(["block", "cyclic"]), variant=st.sampled_from(["plain", "locality", "locality3"]),
+       ncols=st.sampled_from([1, 2, 3, 16]), f32=st.booleans())
+def test_random_decompositions_on_the_gpu(n, R, mx, pf, seed, uneven, ppn, placement, variant, ncols, f32):
+    need_gpu()
+    import torch
+    if variant == "locality3" and placement == "cyclic":
+        placement = "block"   # the 3-step variant needs contiguous node rows
+    R = min(R, n)
+    say("hypothesis", n, R, mx, round(pf, 3), seed, uneven, ppn, placement, variant, ncols, f32)
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn, placement)
+    plans = [D.plan(r, variant) for r in range(R)]
+    plan = gpu_plan(rs, rp, cols, ppn, variant, placement)
+    for r in range(R):
+        assert_plan_equal(plan_rank(plan, r), plans[r], f"rank {r}")
+    dt = torch.float32 if f32 else torch.float64
+    xh = uniform_pm1(seed + 3, n * ncols).reshape(n, ncols)
+    if f32:
+        xh = xh.astype(np.float32)
+    out = OM.forward_all(plans, xh, rs)
+    H = sum(h.size for h in halos)
+    x = dev(xh)
+    halo = torch.full((H, ncols), float("nan"), dtype=dt, device="cuda")
+    b = P.hx_batch_from_plan(plan, x, halo, flags=P.HX_WORLD_SIM_TRANSFER)
+    P.hx_batch_start(b)
+    P.hx_batch_wait(b)
+    send = host(P.batch_arena_view(b, P.HX_ARENA_SEND, ncols, dt))
+    recv = host(P.batch_arena_view(b, P.HX_ARENA_RECV, ncols, dt))
+    for r in range(R):
+        s1 = P.hx_batch_arena_offset(b, P.HX_ARENA_SEND, r)
+        s2 = P.hx_batch_arena_offset(b, P.HX_ARENA_SEND | 2, r)
+        r1 = P.hx_batch_arena_offset(b, P.HX_ARENA_RECV, r)
+        r2 = P.hx_batch_arena_offset(b, P.HX_ARENA_RECV | 2, r)
+        assert bits_equal(send[s1:s1 + out["send1"][r].shape[0]], out["send1"][r]), r
+        assert bits_equal(send[s2:s2 + out["send2"][r].shape[0]], out["send2"][r]), r
+        assert bits_equal(recv[r1:r1 + out["recv1"][r].shape[0]], out["recv1"][r]), r
+        assert bits_equal(recv[r2:r2 + out["recv2"][r].shape[0]], out["recv2"][r]), r
+    want_halo = np.concatenate(out["halo"]) if H else np.zeros((0, ncols), xh.dtype)
+    assert bits_equal(host(halo), want_halo)
+    b.free()
+    # staged backward (the closed form for the plain plan)
+    ex, _ = staged_exchange(rs, rp, cols, ppn, variant, ncols, dt, node_map=placement)
+    g = uniform_pm1(seed + 5, H * ncols).reshape(H, ncols)
+    if f32:
+        g = g.astype(np.float32)
+    gy = np.split(g, np.cumsum([h.size for h in halos])[:-1])
+    want = OM.staged_adjoint_reference(plans, gy, rs)["g_x"]
+    ex.g_halo.copy_(dev(g))
+    P.hx_batch_backward(ex.batch)
+    torch.cuda.synchronize()
+    assert bits_equal(host(ex.g_x), want)
+
+
+@pytest.mark.parametrize("variant", ["plain", "locality"])
+def test_world_without_halo_binds_empty_gradients(variant):
+    """One rank (no halo entries): its empty halo-gradient buffer may be a
+    null pointer; the backward writes +0.0 to every row."""
+    need_gpu()
+    import torch
+    rs, rp, cols = random_small_csr(10, 1, 3, 0.5, 4, False)
+    ex, _ = staged_exchange(rs, rp, cols, 2, variant, 2, torch.float64)
+    assert ex.halo.shape[0] == 0
+    ex.g_x.fill_(float("nan"))
+    P.hx_batch_backward(ex.batch)
+    torch.cuda.synchronize()
+    got = host(ex.g_x)
+    assert np.all(got == 0) and not np.signbit(got).any()
