@@ -90,3 +90,58 @@ def test_world_without_halo_binds_empty_gradients(variant):
     torch.cuda.synchronize()
     got = host(ex.g_x)
     assert np.all(got == 0) and not np.signbit(got).any()
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
+@given(members=st.lists(st.tuples(st.integers(0, 10_000), st.integers(1, 3000), st.integers(1, 200)),
+                        min_size=1, max_size=6),
+       ncols=st.sampled_from([1, 2, 3, 4, 16, 64]), f32=st.booleans(),
+       tile=st.sampled_from([0, 1, 7, 64, 300, 4096]), bt=st.sampled_from([0, 256, 512, 1024]),
+       bpc=st.sampled_from([0, 1, 2, 8, 1 << 20]), unroll=st.sampled_from([0, 1, 2, 4, 8]),
+       nt=st.booleans(), push=st.sampled_from([0, 1, 2]), win=st.sampled_from([0, 1, 2]),
+       pair=st.sampled_from([0, 1, 2]), per_nbr=st.booleans())
+def test_member_batches_under_random_schedules(members, ncols, f32, tile, bt, bpc, unroll, nt, push, win, pair,
+                                                per_nbr):
+    """Batches of requests built from random exchange lists, under a random
+    launch schedule: every member's send arena (pack), halo (unpack of its
+    receive arena) and backward equal the oracle's."""
+    need_gpu()
+    import torch
+    from workloads import batched_plan
+    sched = dict(tile_rows=tile, block_threads=bt, blocks_per_cu=bpc, unroll=unroll, nontemporal=int(nt),
+                 push_pack=push, lds_window=win, pair_rows=pair, per_neighbor=int(per_nbr))
+    if push == 1 and bt == 1024:
+        sched["block_threads"] = 512   # the push pack runs at most 512 lanes
+    say("hypothesis batch", members, ncols, f32, sched)
+    dt = torch.float32 if f32 else torch.float64
+    reqs, keep, want = [], [], []
+    for i, (b, h, k) in enumerate(members):
+        lists = batched_plan(b, h, min(k, h))
+        xh = uniform_pm1(b + 7, h * ncols).reshape(h, ncols)
+        rh = uniform_pm1(b + 8, h * ncols).reshape(h, ncols)
+        gh = uniform_pm1(b + 9, h * ncols).reshape(h, ncols)
+        if f32:
+            xh, rh, gh = xh.astype(np.float32), rh.astype(np.float32), gh.astype(np.float32)
+        x, halo = dev(xh), torch.full((h, ncols), float("nan"), dtype=dt, device="cuda")
+        topo = P.hx_topo_create(0, 4096, lists["procs"], lists["procs"])
+        req = P.hx_neighbor_alltoallv_init(x, lists["counts"], lists["displs"], lists["send_idx"], halo,
+                                           lists["counts"], lists["displs"], topo)
+        P.req_arena_view(req, P.HX_ARENA_RECV, ncols, dt).copy_(dev(rh))
+        g, gx = dev(gh), torch.full_like(x, float("nan"))
+        P.hx_req_bind_grad(req, g, gx)
+        ptr, perm = OP.transpose_csr(lists["send_idx"], h)
+        reqs.append(req)
+        keep.append((x, halo, g, gx, topo))
+        want.append((OM.pack(xh, lists["send_idx"]), rh, OM.pack_transpose(gh, ptr, perm)))
+    batch = P.hx_batch_init(reqs, sched=sched)
+    P.hx_batch_start(batch)
+    P.hx_batch_wait(batch)
+    P.hx_batch_backward(batch)
+    torch.cuda.synchronize()
+    for req, (x, halo, g, gx, topo), (w_send, w_halo, w_gx) in zip(reqs, keep, want):
+        assert bits_equal(host(P.req_arena_view(req, P.HX_ARENA_SEND, ncols, dt)), w_send)
+        assert bits_equal(host(halo), w_halo)
+        assert bits_equal(host(gx), w_gx)
+    batch.free()
+    for req in reqs:
+        req.free()
