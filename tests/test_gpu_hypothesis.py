@@ -145,3 +145,50 @@ def test_member_batches_under_random_schedules(members, ncols, f32, tile, bt, bp
     batch.free()
     for req in reqs:
         req.free()
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
+@given(n=st.integers(2, 400), R=st.integers(2, 20), mx=st.integers(1, 8), pf=st.floats(0.0, 1.0),
+       seed=st.integers(0, 10_000), ppn=st.integers(1, 6), variant=st.sampled_from(["plain", "locality", "locality3"]),
+       ncols=st.sampled_from([1, 2, 5]), f32=st.booleans(),
+       tile=st.sampled_from([0, 3, 64, 1000]), bt=st.sampled_from([0, 256, 1024]),
+       bpc=st.sampled_from([0, 2, 1 << 20]), unroll=st.sampled_from([0, 1, 4]), nt=st.booleans(),
+       win=st.sampled_from([0, 1, 2]), pair=st.sampled_from([0, 1, 2]), direct=st.booleans())
+def test_worlds_under_random_schedules(n, R, mx, pf, seed, ppn, variant, ncols, f32, tile, bt, bpc, unroll, nt, win,
+                                       pair, direct):
+    """A world's exchange and staged backward under a random schedule for all
+    four phases, replayed from graphs or launched directly: halos equal the
+    direct gather, gradients the oracle's staged adjoint."""
+    need_gpu()
+    import torch
+    R = min(R, n)
+    sched = dict(tile_rows=tile, block_threads=bt, blocks_per_cu=bpc, unroll=unroll, nontemporal=int(nt),
+                 lds_window=win, pair_rows=pair, push_pack=2)
+    say("hypothesis world", n, R, mx, round(pf, 3), seed, ppn, variant, ncols, f32, sched, direct)
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, False)
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    plans = [D.plan(r, variant) for r in range(R)]
+    dt = torch.float32 if f32 else torch.float64
+    ex, _ = staged_exchange(rs, rp, cols, ppn, variant, ncols, dt)
+    for ph in range(4):
+        P.hx_batch_set_sched(ex.batch, ph, sched)
+    P.hx_batch_set_replay(ex.batch, P.HX_REPLAY_DIRECT if direct else P.HX_REPLAY_GRAPH)
+    H = ex.halo.shape[0]
+    xh = uniform_pm1(seed + 11, n * ncols).reshape(n, ncols)
+    g = uniform_pm1(seed + 12, H * ncols).reshape(H, ncols)
+    if f32:
+        xh, g = xh.astype(np.float32), g.astype(np.float32)
+    ex.x.copy_(dev(xh))
+    ex.halo.fill_(float("nan"))
+    ex.forward()
+    torch.cuda.synchronize()
+    want_halo = xh[np.concatenate(halos)] if H else np.zeros((0, ncols), xh.dtype)
+    assert bits_equal(host(ex.halo), want_halo)
+    gy = np.split(g, np.cumsum([h.size for h in halos])[:-1])
+    want = OM.staged_adjoint_reference(plans, gy, rs)["g_x"]
+    ex.g_halo.copy_(dev(g))
+    ex.g_x.fill_(float("nan"))
+    ex.backward()
+    torch.cuda.synchronize()
+    assert bits_equal(host(ex.g_x), want)
