@@ -209,3 +209,38 @@ def test_collective_init_random_decompositions(n, R, mx, pf, seed, uneven, ppn, 
     rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
     halos = OP.all_halos(rp, cols, rs)
     run_collective(rs, halos, ppn, variant, node_map, 2, seed + 13, shuffle)
+
+
+@settings(max_examples=30, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
+@given(n=st.integers(1, 500), R=st.integers(1, 20), density=st.floats(0.0, 1.0), seed=st.integers(0, 10_000),
+       uneven=st.booleans(), ppn=st.integers(1, 6), node_map=st.sampled_from(["block", "cyclic"]),
+       variant=st.sampled_from(["plain", "locality", "locality3"]))
+def test_plans_from_arbitrary_halos(n, R, density, seed, uneven, ppn, node_map, variant):
+    """Plans built from halos drawn directly (each rank needs a random subset
+    of the columns it does not own, from none to all), not from a matrix:
+    every field of every rank equals the oracle's."""
+    need_gpu()
+    from workloads import splitmix64
+    if variant == "locality3":
+        node_map = "block"
+    R = min(R, n)
+    if uneven and R > 1:
+        cuts = np.sort((splitmix64(seed, 0, R - 1) % np.uint64(n + 1)).astype(np.int64))
+        rs = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+    else:
+        rs = (np.arange(R + 1, dtype=np.int64) * n) // R
+    z = splitmix64(seed + 1, 0, R * n)
+    u = (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    halos = []
+    for r in range(R):
+        row = u[r * n:(r + 1) * n] < density
+        row[rs[r]:rs[r + 1]] = False
+        halos.append(np.nonzero(row)[0].astype(np.int64))
+    say("hypothesis halos", n, R, round(density, 3), seed, uneven, ppn, node_map, variant)
+    D = OP.Decomposition(halos, rs, ppn, node_map)
+    hp = np.concatenate([[0], np.cumsum([h.size for h in halos])]).astype(np.int64)
+    flat = np.concatenate(halos).astype(np.int32) if hp[-1] else np.zeros(0, np.int32)
+    vid = {"plain": P.HX_PLAIN, "locality": P.HX_LOCALITY_2STEP, "locality3": P.HX_LOCALITY_3STEP}[variant]
+    plan = P.hx_plan_from_halos(R, rs, ppn, vid, hp, dev(flat) if flat.size else None, node_map=node_map)
+    for r in range(R):
+        assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"rank {r}")
