@@ -67,8 +67,8 @@ typedef enum { HX_F32 = 0, HX_F64 = 1 } hx_dtype;
  * node pair, sent by the pair's aggregator A(n,m) = n*ppn + (m mod cnt(n))
  * to its receiver B(n,m) = m*ppn + (n mod cnt(m)); the aggregator packs its
  * node-mates' rows directly (node-shared memory), so its pack indices are
- * rows counted from the node's first row and such plans drive whole-
- * decomposition batches only (hx_req_from_plan returns HX_ERR_UNSUPPORTED). */
+ * rows counted from the node's first row, and a request of such a plan reads
+ * the rows of its rank's whole node (hx_req_from_plan). */
 typedef enum { HX_PLAIN = 0, HX_LOCALITY_2STEP = 1, HX_LOCALITY_3STEP = 2 } hx_variant;
 
 /* Placement of nranks ranks on NN = ceil(nranks / ppn) nodes (Sec. 2.2 groups
@@ -307,7 +307,8 @@ typedef enum {
   HX_F_S1_PROCS,      /* [n_s1]     stage-1 destinations, ascending */
   HX_F_S1_COUNTS,     /* [n_s1] */
   HX_F_S1_DISPLS,     /* [n_s1]     exclusive prefix of counts */
-  HX_F_S1_IDX,        /* [E1]       local row packed into each stage-1 send slot */
+  HX_F_S1_IDX,        /* [E1]       local row packed into each stage-1 send slot (3-step:
+                                      row counted from the node's first row) */
   HX_F_R1_PROCS,      /* [n_r1]     stage-1 sources, ascending */
   HX_F_R1_COUNTS,     /* [n_r1] */
   HX_F_R1_DISPLS,     /* [n_r1] */
@@ -319,7 +320,8 @@ typedef enum {
   HX_F_R2_COUNTS,     /* [n_r2] */
   HX_F_R2_DISPLS,     /* [n_r2] */
   HX_F_UNPACK_SRC,    /* [H]        slot of halo entry j in [stage-1 recv | stage-2 recv] */
-  HX_F_BT_PTR,        /* [n_local+1] transpose of the pack map: row -> slots */
+  HX_F_BT_PTR,        /* [n_local+1] transpose of the pack map: row -> slots (3-step: over
+                                      the node's rows) */
   HX_F_BT_PERM,       /* [E1]       send slots grouped by local row, ascending */
   HX_F_COUNT
 } hx_field;
@@ -340,7 +342,15 @@ int hx_plan_field_all(const hx_plan* plan, hx_field field, int64_t* offsets, int
 int hx_plan_describe(const hx_plan* plan, int* nranks, int64_t* n, hx_info* info, int64_t* row_starts);
 
 /* Persistent request for one rank of a plan (its arrays stay on the device).
- * x_local device [n_local, ncols]; halo device [H, ncols]. */
+ * x_local device [n_local, ncols]: the rank's own rows (n_local of them);
+ * halo device [H, ncols].  For a 3-step plan x_local is instead the first row
+ * of the rank's node in memory the node's ranks share, and n_local the
+ * node's row count: an aggregator packs its node-mates' rows (the on-node
+ * gather of the 3-step scheme).  The backward of such a request then writes
+ * g_x [n_local, ncols] over the node's rows too: this request's share of
+ * their gradient (the sums over its own send slots; rows it never packs get
+ * +0.0), which the node's ranks add up.  HX_ERR_ARG, HX_ERR_RANGE (a plan
+ * whose arrays are inconsistent), HX_ERR_NOMEM, HX_ERR_HIP. */
 int hx_req_from_plan(const hx_plan* plan, int rank, const void* x_local, void* halo,
                      hx_dtype dtype, int ncols, hx_req** out);
 

@@ -150,7 +150,9 @@ extern "C" int hx_comm_create(int nranks, const int64_t* row_starts, const hx_in
   for (int r = 0; r < nranks; ++r)
     if (row_starts[r + 1] < row_starts[r]) return fail(HX_ERR_ARG, "row_starts must be non-decreasing");
   if (info->variant != HX_PLAIN && info->variant != HX_LOCALITY_2STEP)
-    return fail(HX_ERR_UNSUPPORTED, "per-rank requests exist for the plain and 2-step variants");
+    return fail(HX_ERR_UNSUPPORTED,
+                "the collective init builds plain and 2-step requests (a 3-step request reads its node's rows: "
+                "hx_req_from_plan)");
   if (info->ppn < 1) return fail(HX_ERR_ARG, "ppn must be >= 1");
   if (info->node_map != HX_NODES_BLOCK && info->node_map != HX_NODES_CYCLIC) return fail(HX_ERR_ARG, "bad node map");
   auto* c = new (std::nothrow) hx_comm;

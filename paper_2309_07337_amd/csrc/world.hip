@@ -317,14 +317,20 @@ int hx::req_fill_from_plan(const hx_plan* p, int rank, const void* x_local, void
   if (rank < 0 || rank >= p->R) return fail(HX_ERR_RANGE, "rank out of range");
   if (dtype != HX_F32 && dtype != HX_F64) return fail(HX_ERR_ARG, "bad dtype");
   if (ncols <= 0) return fail(HX_ERR_ARG, "ncols must be positive");
-  if (p->variant == HX_LOCALITY_3STEP)
-    return fail(HX_ERR_UNSUPPORTED, "3-step plans pack node-mates' rows: use a whole-decomposition batch");
   r->dtype = dtype;
   r->ncols = ncols;
   r->row_bytes = (size_t)ncols * dtype_bytes(dtype);
   r->variant = p->variant;
   r->rank = rank;
-  r->n_local = p->row_starts[rank + 1] - p->row_starts[rank];
+  if (p->variant == HX_LOCALITY_3STEP) {
+    if (p->node_map != HX_NODES_BLOCK) return fail(HX_ERR_UNSUPPORTED, "3-step plans need block placement");
+    // an aggregator packs its node-mates' rows: the request reads the rows of
+    // its whole node (block placement: ranks nd*ppn .. own them contiguously)
+    const int nd = rank / p->ppn, first = nd * p->ppn, last = std::min(p->R, first + p->ppn);
+    r->n_local = p->row_starts[last] - p->row_starts[first];
+  } else {
+    r->n_local = p->row_starts[rank + 1] - p->row_starts[rank];
+  }
   r->H = p->size(HX_F_HALO, rank);
   r->E1 = p->size(HX_F_S1_IDX, rank);
   r->E2 = p->size(HX_F_S2_SRC, rank);

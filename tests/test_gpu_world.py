@@ -152,8 +152,17 @@ def test_world_random_rows_full_size(dtype_name, variant):
             procs = P.hx_plan_field(plan, r, "s1_procs")
             inter += int(np.sum(procs // 128 != r // 128))
         assert inter == 32 * 31
-        with pytest.raises(P.HXError):
-            P.hx_req_from_plan(plan, 0, dev(xh[:1024]), torch.empty(1, 1, device="cuda", dtype=halo.dtype))
+        # rank 5 aggregates node 0's data for node 5: its own request packs
+        # from the node's rows (node-shared memory)
+        nb = int(rs[128])
+        s1 = P.hx_plan_field(plan, 5, "s1_idx")
+        assert s1.size > 0 and int(s1.max()) >= int(rs[6])   # reads node-mates' rows
+        req = P.hx_req_from_plan(plan, 5, dev(xh[:nb]), torch.empty(halos[5].size, 1, device="cuda", dtype=halo.dtype))
+        P.hx_start(req)
+        P.hx_wait(req)
+        send = host(P.req_arena_view(req, P.HX_ARENA_SEND, 1, halo.dtype))
+        assert bits_equal(send[:s1.size], xh[:nb][s1])
+        req.free()
 
 
 @pytest.mark.parametrize("variant", ["plain", "locality"])
@@ -184,6 +193,66 @@ def test_rank_requests_from_plan(variant):
         assert bits_equal(send, np.concatenate([out["send1"][r], out["send2"][r]]))
         assert bits_equal(host(halo), out["halo"][r])
         req.free()
+
+
+def _node_rows(rs, ppn, r):
+    nd = r // ppn
+    return int(rs[nd * ppn]), int(rs[min(len(rs) - 1, (nd + 1) * ppn)])
+
+
+def _check_3step_requests(rs, rp, cols, ppn, ranks, C, seed):
+    import torch
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    R = len(rs) - 1
+    plans = [D.plan(r, "locality3") for r in range(R)]
+    n = int(rs[-1])
+    xh = uniform_pm1(seed, n * C).reshape(n, C)
+    out = OM.forward_all(plans, xh, rs)
+    plan = gpu_plan(rs, rp, cols, ppn, "locality3")
+    for r in ranks:
+        say("3-step rank request", R, ppn, r)
+        a, b = _node_rows(rs, ppn, r)
+        x_node = dev(xh[a:b])
+        halo = torch.full((halos[r].size, C), float("nan"), dtype=torch.float64, device="cuda")
+        req = P.hx_req_from_plan(plan, r, x_node, halo)
+        P.req_arena_view(req, P.HX_ARENA_RECV, C, torch.float64).copy_(dev(out["arena"][r]))
+        P.hx_start(req)
+        P.hx_wait(req)
+        send = host(P.req_arena_view(req, P.HX_ARENA_SEND, C, torch.float64))
+        assert bits_equal(send, np.concatenate([out["send1"][r], out["send2"][r]])), r
+        assert bits_equal(host(halo), out["halo"][r]), r
+        # the backward of its own pack, over the node's rows
+        E1 = int(plans[r]["s1_idx"].size)
+        gh = uniform_pm1(seed + 1000 + r, E1 * C).reshape(E1, C)
+        g_x = torch.full((b - a, C), float("nan"), dtype=torch.float64, device="cuda")
+        P.hx_req_bind_grad(req, dev(gh), g_x)
+        P.hx_backward(req)
+        assert bits_equal(host(g_x), OM.pack_transpose(gh, plans[r]["bt_ptr"], plans[r]["bt_perm"])), r
+        req.free()
+
+
+def test_rank_requests_from_3step_plan():
+    """One rank's request of a 3-step plan reads the rows of its whole node
+    (node-shared memory: an aggregator packs its node-mates' rows): with the
+    receive arena filled by the oracle's transfer, Start/Wait give the
+    oracle's send arena and halo, and the backward of its pack (over the
+    node's rows) the oracle's transpose sum; on the 27-point grid (64 ranks
+    per node) an aggregator (5), a receiver (64) and ranks that are
+    neither."""
+    need_gpu()
+    rs, rp, cols = cached_grid3d()
+    _check_3step_requests(rs, rp, cols, 64, (0, 5, 64, 219, 300, 511), 3, 23)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_rank_requests_from_3step_plan_tiny(case):
+    """The same on the tiny decompositions (uneven rows, partial last nodes,
+    ranks that own nothing), every rank."""
+    need_gpu()
+    n, R, mx, pf, seed, uneven, ppn = case
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    _check_3step_requests(rs, rp, cols, ppn, range(R), 2, seed + 5)
 
 
 @pytest.mark.parametrize("variant", ["plain", "locality"])
