@@ -228,9 +228,9 @@ int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local,
  * plays every rank of a simulated one:
  *
  * hx_comm_create: nranks ranks owning rows [row_starts[r], row_starts[r+1])
- *   (host [nranks+1], copied), info (host, copied; variant HX_PLAIN or
- *   HX_LOCALITY_2STEP, else HX_ERR_UNSUPPORTED), stream: where the plan is
- *   built when the set completes.
+ *   (host [nranks+1], copied), info (host, copied; any variant, the 3-step
+ *   one with HX_NODES_BLOCK only, else HX_ERR_UNSUPPORTED), stream: where
+ *   the plan is built when the set completes.
  * hx_neighbor_locality_alltoallv_init: rank topo->rank joins.  Arguments as
  *   for hx_neighbor_alltoallv_init (displacements NULL or the prefix sums),
  *   with global indices instead of local rows: global_sindices host
@@ -238,7 +238,10 @@ int hx_neighbor_alltoallv_init(const void* x_local, int64_t n_local,
  *   [sum(recvcounts)] int64, the message from recv_procs[i] holding indices
  *   owned by that rank, distinct over the whole receive list, in any order
  *   (halo row u receives global index global_rindices[u]).  n_local must be
- *   the rank's row count.  Lists are copied.  Until every rank has joined
+ *   the rank's row count; for the 3-step variant x_local is instead the
+ *   first row of the rank's node in node-shared memory and n_local the
+ *   node's row count, as for hx_req_from_plan (send indices stay the rank's
+ *   own rows).  Lists are copied.  Until every rank has joined
  *   the returned request is pending: every call on it but hx_req_free
  *   returns HX_ERR_STATE.  The call that completes the set checks that what
  *   q sends to s is, element for element, what s receives from q, builds the

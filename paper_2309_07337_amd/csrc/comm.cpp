@@ -149,12 +149,12 @@ extern "C" int hx_comm_create(int nranks, const int64_t* row_starts, const hx_in
   if (row_starts[0] != 0) return fail(HX_ERR_ARG, "row_starts[0] must be 0");
   for (int r = 0; r < nranks; ++r)
     if (row_starts[r + 1] < row_starts[r]) return fail(HX_ERR_ARG, "row_starts must be non-decreasing");
-  if (info->variant != HX_PLAIN && info->variant != HX_LOCALITY_2STEP)
-    return fail(HX_ERR_UNSUPPORTED,
-                "the collective init builds plain and 2-step requests (a 3-step request reads its node's rows: "
-                "hx_req_from_plan)");
+  if (info->variant != HX_PLAIN && info->variant != HX_LOCALITY_2STEP && info->variant != HX_LOCALITY_3STEP)
+    return fail(HX_ERR_ARG, "bad variant %d", info->variant);
   if (info->ppn < 1) return fail(HX_ERR_ARG, "ppn must be >= 1");
   if (info->node_map != HX_NODES_BLOCK && info->node_map != HX_NODES_CYCLIC) return fail(HX_ERR_ARG, "bad node map");
+  if (info->variant == HX_LOCALITY_3STEP && info->node_map != HX_NODES_BLOCK)
+    return fail(HX_ERR_UNSUPPORTED, "the 3-step variant needs block placement");
   auto* c = new (std::nothrow) hx_comm;
   if (!c) return fail(HX_ERR_NOMEM, "out of host memory");
   c->R = nranks;
@@ -191,9 +191,16 @@ extern "C" int hx_neighbor_locality_alltoallv_init(const void* x_local, int64_t 
   if (dtype != HX_F32 && dtype != HX_F64) return fail(HX_ERR_ARG, "bad dtype");
   if (ncols <= 0) return fail(HX_ERR_ARG, "ncols must be positive");
   const std::vector<int64_t>& rs = comm->row_starts;
-  if (n_local != rs[r + 1] - rs[r])
-    return fail(HX_ERR_ARG, "rank %d: n_local %lld, but it owns %lld rows", r, (long long)n_local,
-                (long long)(rs[r + 1] - rs[r]));
+  // the vector a request packs from: the rank's rows, or (3-step, where an
+  // aggregator packs its node-mates' rows) its node's rows
+  int64_t want = rs[r + 1] - rs[r];
+  if (comm->info.variant == HX_LOCALITY_3STEP) {
+    const int first = r / comm->info.ppn * comm->info.ppn, last = std::min(comm->R, first + comm->info.ppn);
+    want = rs[last] - rs[first];
+  }
+  if (n_local != want)
+    return fail(HX_ERR_ARG, "rank %d: n_local %lld, but its request packs from %lld rows", r, (long long)n_local,
+                (long long)want);
   int64_t E = 0, H = 0;
   const int ns = (int)topo->send_procs.size(), nr = (int)topo->recv_procs.size();
   HX_TRY(dense_layout(ns, sendcounts, sdispls, &E, "send"));

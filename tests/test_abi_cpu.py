@@ -160,10 +160,24 @@ def test_collective_locality_init_checks_on_host():
     """The per-rank locality-aware init: a joined request is pending (every
     call on it refuses), a rank cannot join twice, and a completing call
     whose ranks' lists do not match fails before any device work, leaving
-    the set over."""
+    the set over.  A 3-step rank packs from its node's rows (block placement
+    only), so its vector has the node's row count."""
     with pytest.raises(P.HXError) as e:
-        P.hx_comm_create(2, [0, 3, 6], 1, P.HX_LOCALITY_3STEP, stream=0)
+        P.hx_comm_create(2, [0, 3, 6], 1, P.HX_LOCALITY_3STEP, node_map="cyclic", stream=0)
     assert e.value.code == P.HX_ERR_UNSUPPORTED
+    comm3 = P.hx_comm_create(2, [0, 3, 6], 2, P.HX_LOCALITY_3STEP, stream=0)
+    t0 = P.hx_topo_create(0, 2, [1], [1])
+    with pytest.raises(P.HXError) as e:       # its own 3 rows, not the node's 6
+        P.hx_neighbor_locality_alltoallv_init(FakeTensor(3), [1], None, [1], FakeTensor(2), [2], None, [3, 4],
+                                              t0, comm3)
+    assert e.value.code == P.HX_ERR_ARG
+    r3 = P.hx_neighbor_locality_alltoallv_init(FakeTensor(6), [1], None, [1], FakeTensor(2), [2], None, [3, 4],
+                                               t0, comm3)
+    with pytest.raises(P.HXError) as e:
+        P.hx_start(r3, stream=0)
+    assert e.value.code == P.HX_ERR_STATE
+    r3.free()
+    comm3.free()
     with pytest.raises(P.HXError) as e:
         P.hx_comm_create(2, [0, 3, 6], 1, P.HX_LOCALITY_2STEP, node_map=5, stream=0)
     assert e.value.code == P.HX_ERR_ARG

@@ -48,7 +48,8 @@ def run_collective(rs, halos, ppn, variant, node_map, C, seed, shuffle):
     D = OP.Decomposition(halos, rs, ppn, node_map)
     out = OM.forward_all([D.plan(r, variant) for r in range(R)], xh, rs)
     recv, send = rank_lists(halos, rs, seed, shuffle)
-    comm = P.hx_comm_create(R, rs, ppn, P.HX_PLAIN if variant == "plain" else P.HX_LOCALITY_2STEP, node_map)
+    var_id = {"plain": P.HX_PLAIN, "locality": P.HX_LOCALITY_2STEP, "locality3": P.HX_LOCALITY_3STEP}[variant]
+    comm = P.hx_comm_create(R, rs, ppn, var_id, node_map)
     order = np.random.default_rng(seed + 1).permutation(R)
     reqs, keep = {}, []
     for k, r in enumerate(order):
@@ -56,7 +57,11 @@ def run_collective(rs, halos, ppn, variant, node_map, C, seed, shuffle):
         topo = P.hx_topo_create(r, R, [q for q, _ in recv[r]], [s for s, _ in send[r]])
         rind = np.concatenate([v for _, v in recv[r]]) if recv[r] else np.zeros(0, np.int64)
         sind = np.concatenate([v for _, v in send[r]]) if send[r] else np.zeros(0, np.int64)
-        x_local = dev(xh[rs[r]:rs[r + 1]])
+        if variant == "locality3":   # an aggregator packs its node-mates' rows: the node's rows
+            nd = r // ppn
+            x_local = dev(xh[rs[nd * ppn]:rs[min(R, (nd + 1) * ppn)]])
+        else:
+            x_local = dev(xh[rs[r]:rs[r + 1]])
         halo = torch.full((rind.size, C), float("nan"), dtype=torch.float64, device="cuda")
         req = P.hx_neighbor_locality_alltoallv_init(x_local, [v.size for _, v in send[r]], None, sind, halo,
                                                     [v.size for _, v in recv[r]], None, rind, topo, comm)
@@ -78,7 +83,8 @@ def run_collective(rs, halos, ppn, variant, node_map, C, seed, shuffle):
     comm.free()
 
 
-@pytest.mark.parametrize("variant,node_map", [("plain", "block"), ("locality", "block"), ("locality", "cyclic")])
+@pytest.mark.parametrize("variant,node_map", [("plain", "block"), ("locality", "block"), ("locality", "cyclic"),
+                                              ("locality3", "block")])
 @pytest.mark.parametrize("case", CASES)
 def test_tiny_decompositions(case, variant, node_map):
     need_gpu()
@@ -99,10 +105,11 @@ def test_grid2d(node_map):
     run_collective(rs, halos, 4, "locality", node_map, 1, 31, True)
 
 
-def test_grid3d():
+@pytest.mark.parametrize("variant", ["locality", "locality3"])
+def test_grid3d(variant):
     """27-point 128^3, 512 ranks joining in a random order, receive orders shuffled."""
     need_gpu()
     rs, rp, cols = cached_grid3d()
     halos = OP.all_halos(rp, cols, rs)
-    say("collective init grid3d")
-    run_collective(rs, halos, 64, "locality", "block", 2, 41, True)
+    say("collective init grid3d", variant)
+    run_collective(rs, halos, 64, variant, "block", 2, 41, True)

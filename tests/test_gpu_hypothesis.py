@@ -197,14 +197,17 @@ def test_worlds_under_random_schedules(n, R, mx, pf, seed, ppn, variant, ncols, 
 @settings(max_examples=25, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
 @given(n=st.integers(2, 300), R=st.integers(1, 16), mx=st.integers(1, 6), pf=st.floats(0.0, 1.0),
        seed=st.integers(0, 10_000), uneven=st.booleans(), ppn=st.integers(1, 5),
-       node_map=st.sampled_from(["block", "cyclic"]), variant=st.sampled_from(["plain", "locality"]),
+       node_map=st.sampled_from(["block", "cyclic"]), variant=st.sampled_from(["plain", "locality", "locality3"]),
        shuffle=st.booleans())
 def test_collective_init_random_decompositions(n, R, mx, pf, seed, uneven, ppn, node_map, variant, shuffle):
     """The per-rank locality-aware init on random decompositions, ranks
-    joining in a random order with (optionally) shuffled receive orders."""
+    joining in a random order with (optionally) shuffled receive orders
+    (3-step ranks join with their node's rows)."""
     need_gpu()
     from tests.test_gpu_comm import run_collective
     R = min(R, n)
+    if variant == "locality3":
+        node_map = "block"   # the 3-step variant needs contiguous node rows
     say("hypothesis collective init", n, R, mx, round(pf, 3), seed, uneven, ppn, node_map, variant, shuffle)
     rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
     halos = OP.all_halos(rp, cols, rs)
