@@ -14,7 +14,8 @@
  *   - Sec. 2.4: the calls accept device memory, so packing a send buffer from
  *     a vector and unpacking received data into the halo are device gathers.
  *
- * Start packs (indexed row gather from the local vector); Wait runs the
+ * Start packs (indexed row gather from the local vector, or for the 3-step
+ * variant from the rows of the rank's node); Wait runs the
  * on-node redistribution pack (locality variant) and unpacks into the halo.
  * The message transfer itself is not part of this library: a request exposes
  * its send and receive arenas, and a whole-decomposition batch ("world")
@@ -37,8 +38,9 @@
  *     the unit every list indexes.  All index arrays are int32; every
  *     arena, halo, vector and plan must stay below 2^31 rows.
  *   - Global ownership is contiguous: rank p owns the rows/columns
- *     [row_starts[p], row_starts[p+1]).  Nodes are blocks of ppn consecutive
- *     ranks (the last node may be partial).
+ *     [row_starts[p], row_starts[p+1]).  Ranks sit on nodes of ppn ranks
+ *     (the last node may be partial) as the plan's node map places them
+ *     (hx_info: blocks of consecutive ranks, or round robin).
  */
 #ifndef HX_H
 #define HX_H
