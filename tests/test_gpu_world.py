@@ -255,6 +255,55 @@ def test_rank_requests_from_3step_plan_tiny(case):
     _check_3step_requests(rs, rp, cols, ppn, range(R), 2, seed + 5)
 
 
+@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[4]])
+def test_3step_requests_in_a_member_batch(case):
+    """Every rank's 3-step request (each reading its node's rows, with ranks
+    of one node sharing one copy of them) in one member batch: the batched
+    pack, redistribution and unpack (receive arenas filled by the oracle's
+    transfer) and the batched backward of every request's pack equal the
+    oracle bit for bit."""
+    need_gpu()
+    import torch
+    n, R, mx, pf, seed, uneven, ppn = case
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    halos = OP.all_halos(rp, cols, rs)
+    D = OP.Decomposition(halos, rs, ppn)
+    plans = [D.plan(r, "locality3") for r in range(R)]
+    C = 2
+    xh = uniform_pm1(seed + 3, int(rs[-1]) * C).reshape(-1, C)
+    out = OM.forward_all(plans, xh, rs)
+    plan = gpu_plan(rs, rp, cols, ppn, "locality3")
+    nodes = {}
+    reqs, halos_d, gs, gxs = [], [], [], []
+    for r in range(R):
+        a, b = _node_rows(rs, ppn, r)
+        if r // ppn not in nodes:
+            nodes[r // ppn] = dev(xh[a:b])
+        halo = torch.full((halos[r].size, C), float("nan"), dtype=torch.float64, device="cuda")
+        req = P.hx_req_from_plan(plan, r, nodes[r // ppn], halo)
+        E1 = int(plans[r]["s1_idx"].size)
+        g = dev(uniform_pm1(seed + 500 + r, E1 * C).reshape(E1, C))
+        g_x = torch.full((b - a, C), float("nan"), dtype=torch.float64, device="cuda")
+        P.hx_req_bind_grad(req, g, g_x)
+        reqs.append(req); halos_d.append(halo); gs.append(g); gxs.append(g_x)
+    bt = P.hx_batch_init(reqs)
+    for r in range(R):
+        P.req_arena_view(reqs[r], P.HX_ARENA_RECV, C, torch.float64).copy_(dev(out["arena"][r]))
+    say("3-step member batch", case)
+    P.hx_batch_start(bt)
+    P.hx_batch_wait(bt)
+    P.hx_batch_backward(bt)
+    for r in range(R):
+        send = host(P.req_arena_view(reqs[r], P.HX_ARENA_SEND, C, torch.float64))
+        assert bits_equal(send, np.concatenate([out["send1"][r], out["send2"][r]])), r
+        assert bits_equal(host(halos_d[r]), out["halo"][r]), r
+        want = OM.pack_transpose(host(gs[r]), plans[r]["bt_ptr"], plans[r]["bt_perm"])
+        assert bits_equal(host(gxs[r]), want), r
+    bt.free()
+    for q in reqs:
+        q.free()
+
+
 @pytest.mark.parametrize("variant", ["plain", "locality"])
 def test_launch_phase_matches_graphs(variant):
     """Each phase's kernel launched alone rewrites exactly what the graphs wrote."""
