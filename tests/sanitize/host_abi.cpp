@@ -1,6 +1,7 @@
 // Host paths of the C ABI under AddressSanitizer and UndefinedBehaviorSanitizer:
 // argument validation, topology handles, the allocator hook and its
-// out-of-memory path, plan describe/free on null handles.  None of these
+// out-of-memory path, plan describe/free on null handles, the collective
+// per-rank init's joins, checks and free orders.  None of these
 // calls reach the GPU, so the program runs on a machine without one.  Each
 // check prints what it tested; any failed expectation or sanitizer report
 // ends the program with a non-zero status.
@@ -90,6 +91,55 @@ int main() {
          "more ranks than the dense tables allow");
   EXPECT(p == nullptr, "no plan on error");
   EXPECT(hx_plan_describe(nullptr, nullptr, nullptr, nullptr, nullptr) == HX_ERR_ARG, "describe a null plan");
+
+  // the collective per-rank init: joins and their host checks, a set whose
+  // lists disagree (it fails before any device work), both orders of
+  // freeing a pending request and its communicator
+  {
+    const int64_t crs[3] = {0, 3, 6};
+    hx_info ci{HX_LOCALITY_2STEP, 1, HX_NODES_BLOCK};
+    hx_comm* c = nullptr;
+    EXPECT(hx_comm_create(2, crs, &ci, nullptr, &c) == HX_SUCCESS && c, "communicator created");
+    hx_topo *t0 = nullptr, *t1 = nullptr;
+    const int to1[1] = {1}, to0[1] = {0};
+    EXPECT(hx_topo_create(0, 2, 1, to1, nullptr, 1, to1, nullptr, 0, &t0) == HX_SUCCESS &&
+               hx_topo_create(1, 2, 1, to0, nullptr, 1, to0, nullptr, 0, &t1) == HX_SUCCESS,
+           "topologies of two ranks");
+    const int one[1] = {1}, two[1] = {2};
+    const int64_t s0[1] = {1}, r0[2] = {3, 4}, s1[2] = {3, 4}, r1[1] = {0};
+    hx_req *q0 = nullptr, *q1 = nullptr, *again = nullptr;
+    EXPECT(hx_neighbor_locality_alltoallv_init(x, 3, one, nullptr, s0, h, two, nullptr, r0, HX_F64, 1, t0, c, &q0) ==
+                   HX_SUCCESS && q0,
+           "rank 0 joins, pending");
+    EXPECT(hx_start(q0, nullptr) == HX_ERR_STATE, "a pending request refuses Start");
+    EXPECT(hx_neighbor_locality_alltoallv_init(x, 3, one, nullptr, s0, h, two, nullptr, r0, HX_F64, 1, t0, c,
+                                               &again) == HX_ERR_STATE && !again,
+           "a rank joins once");
+    EXPECT(hx_neighbor_locality_alltoallv_init(x, 3, two, nullptr, s1, h, one, nullptr, r1, HX_F64, 1, t1, c, &q1) ==
+                   HX_ERR_ARG && !q1,
+           "lists that disagree fail before device work");
+    EXPECT(hx_req_free(&q0) == HX_SUCCESS && !q0, "pending request freed before its communicator");
+    EXPECT(hx_comm_free(&c) == HX_SUCCESS && !c, "communicator freed");
+    EXPECT(hx_comm_create(2, crs, &ci, nullptr, &c) == HX_SUCCESS, "second communicator");
+    EXPECT(hx_neighbor_locality_alltoallv_init(x, 3, one, nullptr, s0, h, two, nullptr, r0, HX_F64, 1, t0, c, &q0) ==
+               HX_SUCCESS,
+           "rank 0 joins the second");
+    EXPECT(hx_comm_free(&c) == HX_SUCCESS, "communicator freed with a request still pending");
+    EXPECT(hx_start(q0, nullptr) == HX_ERR_STATE && hx_req_free(&q0) == HX_SUCCESS, "the orphan stays pending, then frees");
+    // 3-step: a rank's request packs from its node's rows (both ranks on one node: 6 rows)
+    ci = hx_info{HX_LOCALITY_3STEP, 2, HX_NODES_BLOCK};
+    EXPECT(hx_comm_create(2, crs, &ci, nullptr, &c) == HX_SUCCESS, "3-step communicator");
+    EXPECT(hx_neighbor_locality_alltoallv_init(x, 3, one, nullptr, s0, h, two, nullptr, r0, HX_F64, 1, t0, c, &q0) ==
+               HX_ERR_ARG,
+           "3-step: the rank's own row count refused");
+    EXPECT(hx_neighbor_locality_alltoallv_init(x, 6, one, nullptr, s0, h, two, nullptr, r0, HX_F64, 1, t0, c, &q0) ==
+               HX_SUCCESS,
+           "3-step: the node's row count");
+    EXPECT(hx_req_free(&q0) == HX_SUCCESS && hx_comm_free(&c) == HX_SUCCESS, "3-step request and communicator freed");
+    ci.node_map = HX_NODES_CYCLIC;
+    EXPECT(hx_comm_create(2, crs, &ci, nullptr, &c) == HX_ERR_UNSUPPORTED && !c, "3-step with a cyclic map refused");
+    EXPECT(hx_topo_free(&t0) == HX_SUCCESS && hx_topo_free(&t1) == HX_SUCCESS, "topologies freed");
+  }
 
   // freeing null handles is allowed
   EXPECT(hx_plan_free(&p) == HX_SUCCESS && hx_req_free(&r) == HX_SUCCESS, "free null handles");
