@@ -333,22 +333,26 @@ def test_staged_backward_random_rows_exact_values():
         assert got[c] == float(np.sum(gh[order[lo:hi]]))
 
 
-def test_staged_backward_random_rows_fp32_by_definition():
-    """2^22 x 32, 4096 ranks, 2-step locality plan, one FP32 value per row:
-    the staged backward at full size (with the simulated reverse transfers),
-    every owned row of a dozen ranks recomputed from the stages' definition
-    (reading R15) by walking the plan's lists: each stage-1 send slot of the
-    row, ascending, contributes its receiver's stage-1 receive-slot sum, which
-    is the receiver's own halo term (if its halo reads the slot) followed by
-    the gradients of the redistribution entries forwarding that slot, in
-    ascending entry, each being the gradient of the halo entry its destination
-    unpacks it into; all additions sequential in FP32."""
+@pytest.mark.parametrize("variant", ["locality", "locality3"])
+def test_staged_backward_random_rows_fp32_by_definition(variant):
+    """2^22 x 32, 4096 ranks, 2-step or 3-step locality plan, one FP32 value
+    per row: the staged backward at full size (with the simulated reverse
+    transfers), every owned row of a dozen ranks recomputed from the stages'
+    definition (reading R15) by walking the plan's lists: each stage-1 send
+    slot that packs the row (3-step: the slots of every rank of its node, in
+    ascending rank, then slot), ascending, contributes its receiver's stage-1
+    receive-slot sum, which is the receiver's own halo term (if its halo
+    reads the slot) followed by the gradients of the redistribution entries
+    forwarding that slot, in ascending entry, each being the gradient of the
+    halo entry its destination unpacks it into; all additions sequential in
+    FP32."""
     need_gpu()
     import torch
     from paper_2309_07337_amd.autograd import HaloExchange
     rs, rp, cols = cached_random_rows()
-    say("staged backward random_rows by definition")
-    plan = gpu_plan(rs, rp, cols, 128, "locality")
+    say("staged backward random_rows by definition", variant)
+    ppn = 128
+    plan = gpu_plan(rs, rp, cols, ppn, variant)
     R, n = len(rs) - 1, int(rs[-1])
     hsz = np.array([P.hx_plan_field(plan, r, "halo").size for r in range(R)], np.int64)
     hoff = np.concatenate([[0], np.cumsum(hsz)])
@@ -376,6 +380,16 @@ def test_staged_backward_random_rows_fp32_by_definition():
             cache[key] = inv
         return cache[key]
 
+    def forwards(t, q):
+        """Redistribution entries of t that forward its stage-1 slot q, ascending."""
+        key = (t, "fwd")
+        if key not in cache:
+            s2src = F(t, "s2_src")
+            o = np.argsort(s2src, kind="stable")
+            cache[key] = (o, s2src[o])
+        o, srt = cache[key]
+        return o[np.searchsorted(srt, q):np.searchsorted(srt, q, side="right")]
+
     def seq_sum(vals):
         acc = np.float32(vals[0])
         for v in vals[1:]:
@@ -387,8 +401,8 @@ def test_staged_backward_random_rows_fp32_by_definition():
         own = inv_unpack(t)[q]
         if own >= 0:
             terms.append(gh[hoff[t] + own])
-        s2src, s2d, s2p = F(t, "s2_src"), F(t, "s2_displs"), F(t, "s2_procs")
-        for e in np.nonzero(s2src == q)[0]:
+        s2d, s2p = F(t, "s2_displs"), F(t, "s2_procs")
+        for e in forwards(t, q):
             m2 = int(np.searchsorted(s2d, e, side="right") - 1)
             d = int(s2p[m2])
             pos = int(np.nonzero(F(d, "r2_procs") == t)[0][0])
@@ -399,24 +413,39 @@ def test_staged_backward_random_rows_fp32_by_definition():
         assert terms, (t, q)
         return seq_sum(terms)
 
+    def packers(r):
+        """(rank, global row of each of its send slots) of the ranks whose packs read r's rows."""
+        if variant == "locality":
+            return [(r, int(rs[r]) + F(r, "s1_idx"))]
+        nd = r // ppn
+        base = int(rs[nd * ppn])
+        return [(q, base + F(q, "s1_idx")) for q in range(nd * ppn, min(R, (nd + 1) * ppn))]
+
     checked = 0
     for r in (0, 1, 1511, 2048, 2300, 4095, 777, 3001, 127, 128, 3968, 1023):
-        s1i, s1d, s1p = F(r, "s1_idx"), F(r, "s1_displs"), F(r, "s1_procs")
-        order = np.argsort(s1i, kind="stable")
-        bounds = np.searchsorted(s1i[order], np.arange(int(rs[r + 1] - rs[r]) + 1))
+        # every send slot packing one of r's rows, in ascending (rank, slot)
+        q_all, k_all, row_all = [], [], []
+        for q, rows in packers(r):
+            sel = np.nonzero((rows >= rs[r]) & (rows < rs[r + 1]))[0]
+            q_all.append(np.full(sel.size, q)); k_all.append(sel); row_all.append(rows[sel])
+        q_all, k_all, row_all = np.concatenate(q_all), np.concatenate(k_all), np.concatenate(row_all)
+        order = np.argsort(row_all, kind="stable")
+        bounds = np.searchsorted(row_all[order], np.arange(int(rs[r]), int(rs[r + 1]) + 1))
         for lc in range(int(rs[r + 1] - rs[r])):
-            slots = order[bounds[lc]:bounds[lc + 1]]      # ascending slot
-            if slots.size == 0:
+            sl = order[bounds[lc]:bounds[lc + 1]]          # ascending (rank, slot)
+            if sl.size == 0:
                 want = np.float32(0.0)
             else:
                 parts = []
-                for k in slots:
+                for i in sl:
+                    q, k = int(q_all[i]), int(k_all[i])
+                    s1d, s1p = F(q, "s1_displs"), F(q, "s1_procs")
                     m = int(np.searchsorted(s1d, k, side="right") - 1)
                     t = int(s1p[m])
-                    pos = int(np.nonzero(F(t, "r1_procs") == r)[0][0])
+                    pos = int(np.nonzero(F(t, "r1_procs") == q)[0][0])
                     parts.append(recv1_slot_sum(t, int(F(t, "r1_displs")[pos]) + int(k - s1d[m])))
                 want = seq_sum(parts)
             c = int(rs[r]) + lc
-            assert got[c].view(np.uint32) == np.float32(want).view(np.uint32), (r, lc, slots.size)
+            assert got[c].view(np.uint32) == np.float32(want).view(np.uint32), (variant, r, lc, sl.size)
             checked += 1
     say("  rows checked:", checked)
