@@ -738,6 +738,7 @@ static std::string cache_key(const hx_batch* b, int phase) {
   k << arch_name() << "|p" << phase << "|t" << b->dtype << "|rb" << b->row_bytes << "|r" << ilog2(rows + 1)
     << "|j" << ilog2(njobs + 1) << "|w" << (b->world ? 1 : 0);
   if (b->world) k << "|v" << b->variant;  // 2-step and 3-step worlds differ in shape
+  if (phase == PH_BWD && b->staged_bwd) k << "|staged";  // forwarder + owner sums, not the closed form
   return k.str();
 }
 

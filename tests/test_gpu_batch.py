@@ -168,6 +168,42 @@ def test_tuner_keeps_results_and_caches(tmp_path, monkeypatch):
     check_members(mem, 16, torch.float64)
 
 
+def test_tuning_cache_keeps_the_staged_backward_apart(tmp_path, monkeypatch):
+    """A locality world's staged backward (forwarder sums, then owner sums)
+    runs other kernels than its closed-form backward: each is tuned and
+    cached under a key of its own, and a new world of either kind picks up
+    its own schedule."""
+    need_gpu()
+    import torch
+    from tests.conftest import cached_grid2d
+    from tests.gpu_util import gpu_plan
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HX_TUNE_CACHE", str(cache))
+    rs, rp, cols = cached_grid2d()
+    plan = gpu_plan(rs, rp, cols, 4, "locality")
+    n = int(rs[-1])
+    H = sum(int(P.hx_plan_field(plan, r, "halo").size) for r in range(len(rs) - 1))
+    keep, tuned = [], {}
+    for staged in (True, False):
+        x = torch.zeros(n, 1, dtype=torch.float64, device="cuda")
+        halo = torch.zeros(H, 1, dtype=torch.float64, device="cuda")
+        g_halo, g_x = torch.ones_like(halo), torch.zeros_like(x)
+        b = P.hx_batch_from_plan(plan, x, halo, flags=P.HX_WORLD_STAGED_BACKWARD if staged else 0)
+        P.hx_batch_bind_grad(b, g_halo, g_x)
+        P.hx_batch_tune(b)
+        tuned[staged] = P.hx_batch_get_sched(b, 3)
+        keep += [b, x, halo, g_halo, g_x]
+    keys = [ln.split()[0] for ln in cache.read_text().splitlines() if "|p3|" in ln.split()[0]]
+    assert any(k.endswith("|staged") for k in keys) and any(not k.endswith("|staged") for k in keys), keys
+    for staged in (True, False):
+        x = torch.zeros(n, 1, dtype=torch.float64, device="cuda")
+        halo = torch.zeros(H, 1, dtype=torch.float64, device="cuda")
+        b = P.hx_batch_from_plan(plan, x, halo, flags=P.HX_WORLD_STAGED_BACKWARD if staged else 0)
+        P.hx_batch_bind_grad(b, torch.ones_like(halo), torch.zeros_like(x))
+        assert P.hx_batch_get_sched(b, 3) == tuned[staged], staged
+        b.free()
+
+
 def test_batch_state_machine():
     need_gpu()
     import torch
