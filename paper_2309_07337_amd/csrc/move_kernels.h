@@ -701,11 +701,12 @@ __device__ __forceinline__ void segsum_body(const SegSumJob* __restrict__ jobs, 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
               const int e = min(base + u * rows_per_pass, eb - 1);  // valid load, no branch
+              // (streaming loads under NT: a term is read once)
               const V* sp = reinterpret_cast<const V*>(term_row(in, in2, split, s_idx[e], rb));
 #pragma unroll
               for (int k = 0; k < NVPL; ++k) {
                 const int vi = lane_v + k * LPR;
-                if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
+                if (NV % LPR == 0 || vi < NV) v[u][k] = ldv<V, NT>(sp + vi);
               }
             }
 #pragma unroll
