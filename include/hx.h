@@ -114,8 +114,8 @@ typedef struct {
                          one workgroup per tile, dispatched by the hardware
                          in tile order */
   int nontemporal;    /* 1: streaming (non-temporal) loads/stores of index and
-                         output (and, in the chunked segmented sum, of the
-                         terms, each read once) */
+                         output (and of the terms in the chunked segmented
+                         sum, and of the source rows in the push pack) */
   int per_neighbor;   /* see above */
   int unroll;         /* rows per lane in flight: 1, 2 or 4 (0 = default);
                          with pair_rows = 1, 16-byte row groups per lane */

@@ -496,11 +496,13 @@ __device__ __forceinline__ void scatter_body(const SegSumJob* __restrict__ jobs,
           for (int u = 0; u < U; ++u) {
             const int e = min(base + u * rows_per_pass, ne - 1);
             dsl[u] = s_idx[e];
+            // (streaming loads under NT: the row's entries sit together, so
+            // its reads coalesce in one pass rather than hit the cache later)
             const HX_G V* sp = reinterpret_cast<const HX_G V*>(in + (r0 + s_row[e]) * (int64_t)rb);
 #pragma unroll
             for (int k = 0; k < NVPL; ++k) {
               const int vi = lane_v + k * LPR;
-              if (NV % LPR == 0 || vi < NV) v[u][k] = sp[vi];
+              if (NV % LPR == 0 || vi < NV) v[u][k] = ldv<V, NT>(sp + vi);
             }
           }
 #pragma unroll
