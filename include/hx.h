@@ -82,7 +82,9 @@ typedef enum { HX_PLAIN = 0, HX_LOCALITY_2STEP = 1, HX_LOCALITY_3STEP = 2 } hx_v
 typedef enum { HX_NODES_BLOCK = 0, HX_NODES_CYCLIC = 1 } hx_node_map;
 
 /* Options of a plan (the info argument of a persistent init, Listing 4):
- * variant (an hx_variant); ppn >= 1 ranks per node (ignored by HX_PLAIN);
+ * variant (an hx_variant); ppn >= 1 ranks per node (ignored by HX_PLAIN; a
+ * value above the rank count means one node of every rank, and a plan
+ * records it as the rank count);
  * node_map (an hx_node_map; the 3-step variant needs HX_NODES_BLOCK, since
  * its aggregator packs its node's rows as one contiguous range,
  * HX_ERR_UNSUPPORTED otherwise).  The fields are plain ints so that any

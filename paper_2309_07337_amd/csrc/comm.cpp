@@ -160,6 +160,7 @@ extern "C" int hx_comm_create(int nranks, const int64_t* row_starts, const hx_in
   c->R = nranks;
   c->row_starts.assign(row_starts, row_starts + nranks + 1);
   c->info = *info;
+  c->info.ppn = std::min(info->ppn, nranks);  // (as a plan does: one node of every rank)
   c->stream = (hipStream_t)stream;
   c->slot.resize(nranks);
   *out = c;
@@ -195,7 +196,8 @@ extern "C" int hx_neighbor_locality_alltoallv_init(const void* x_local, int64_t 
   // aggregator packs its node-mates' rows) its node's rows
   int64_t want = rs[r + 1] - rs[r];
   if (comm->info.variant == HX_LOCALITY_3STEP) {
-    const int first = r / comm->info.ppn * comm->info.ppn, last = std::min(comm->R, first + comm->info.ppn);
+    const int first = r / comm->info.ppn * comm->info.ppn;
+    const int last = (int)std::min<int64_t>(comm->R, (int64_t)first + comm->info.ppn);
     want = rs[last] - rs[first];
   }
   if (n_local != want)

@@ -991,7 +991,9 @@ int plan_alloc(int nranks, const int64_t* row_starts, const hx_info* info, std::
   p->reset(new (std::nothrow) hx_plan);
   if (!*p) return fail(HX_ERR_NOMEM, "out of host memory");
   (*p)->R = nranks;
-  (*p)->ppn = info->ppn;
+  // more ranks per node than ranks is one node of every rank (under either
+  // map); clamping keeps every node-index product inside int
+  (*p)->ppn = std::min(info->ppn, nranks);
   (*p)->node_map = info->node_map;
   (*p)->variant = info->variant;
   (*p)->n = row_starts[nranks];

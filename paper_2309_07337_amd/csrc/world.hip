@@ -326,7 +326,8 @@ int hx::req_fill_from_plan(const hx_plan* p, int rank, const void* x_local, void
     if (p->node_map != HX_NODES_BLOCK) return fail(HX_ERR_UNSUPPORTED, "3-step plans need block placement");
     // an aggregator packs its node-mates' rows: the request reads the rows of
     // its whole node (block placement: ranks nd*ppn .. own them contiguously)
-    const int nd = rank / p->ppn, first = nd * p->ppn, last = std::min(p->R, first + p->ppn);
+    const int first = rank / p->ppn * p->ppn;
+    const int last = (int)std::min<int64_t>(p->R, (int64_t)first + p->ppn);
     r->n_local = p->row_starts[last] - p->row_starts[first];
   } else {
     r->n_local = p->row_starts[rank + 1] - p->row_starts[rank];

@@ -136,6 +136,13 @@ int main() {
                HX_SUCCESS,
            "3-step: the node's row count");
     EXPECT(hx_req_free(&q0) == HX_SUCCESS && hx_comm_free(&c) == HX_SUCCESS, "3-step request and communicator freed");
+    // more ranks per node than ranks: one node of every rank (no int overflow on the way)
+    ci = hx_info{HX_LOCALITY_3STEP, 2147483647, HX_NODES_BLOCK};
+    EXPECT(hx_comm_create(2, crs, &ci, nullptr, &c) == HX_SUCCESS, "3-step communicator, ppn INT_MAX");
+    EXPECT(hx_neighbor_locality_alltoallv_init(x, 6, one, nullptr, s0, h, two, nullptr, r0, HX_F64, 1, t0, c, &q0) ==
+               HX_SUCCESS,
+           "ppn INT_MAX: the node's rows are every row");
+    EXPECT(hx_req_free(&q0) == HX_SUCCESS && hx_comm_free(&c) == HX_SUCCESS, "freed");
     ci.node_map = HX_NODES_CYCLIC;
     EXPECT(hx_comm_create(2, crs, &ci, nullptr, &c) == HX_ERR_UNSUPPORTED && !c, "3-step with a cyclic map refused");
     EXPECT(hx_topo_free(&t0) == HX_SUCCESS && hx_topo_free(&t1) == HX_SUCCESS, "topologies freed");

@@ -32,6 +32,22 @@ def test_tiny_decompositions(case, variant):
         assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"rank {r}")
 
 
+@pytest.mark.parametrize("variant,node_map", [("locality", "block"), ("locality", "cyclic"), ("locality3", "block")])
+def test_more_ranks_per_node_than_ranks(variant, node_map):
+    """ppn above the rank count (up to INT32_MAX) is one node of every rank:
+    the plan equals the oracle's for ppn = R, and records R."""
+    need_gpu()
+    n, R, mx, pf, seed, uneven, ppn = CASES[5]
+    rs, rp, cols = random_small_csr(n, R, mx, pf, seed, uneven)
+    D = OP.Decomposition(OP.all_halos(rp, cols, rs), rs, R, node_map)
+    for big in (R + 1, 1000, 2 ** 31 - 1):
+        say("plan ppn", variant, node_map, big)
+        plan = gpu_plan(rs, rp, cols, big, variant, node_map)
+        assert P.hx_plan_describe(plan)["ppn"] == R
+        for r in range(R):
+            assert_plan_equal(plan_rank(plan, r), D.plan(r, variant), f"ppn {big}, rank {r}")
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_more_random_shapes(seed):
     need_gpu()
