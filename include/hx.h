@@ -117,7 +117,10 @@ typedef struct {
                          in tile order */
   int nontemporal;    /* 1: streaming (non-temporal) loads/stores of index and
                          output (and of the terms in the chunked segmented
-                         sum, and of the source rows in the push pack) */
+                         sum, and of the source rows in the push pack);
+                         2: as 1, and gathers of 4- or 8-byte rows in
+                         16-byte groups also stage their LDS windows with
+                         streaming loads */
   int per_neighbor;   /* see above */
   int unroll;         /* rows per lane in flight: 1, 2 or 4 (0 = default);
                          with pair_rows = 1, 16-byte row groups per lane */

@@ -18,20 +18,21 @@ namespace {
   template <int RB, int U, bool NT, bool GAS>                                                  \
   __global__ void __launch_bounds__(1024)                                                      \
       NAME##_vec(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts, int njobs, \
-                 int64_t ntiles, int tile_rows) {                                              \
-    gather_vec_body<RB, U, NT, GAS>(jobs, ts, njobs, ntiles, tile_rows);                       \
+                 int64_t ntiles, int tile_rows, int stream_win) {                              \
+    gather_vec_body<RB, U, NT, GAS>(jobs, ts, njobs, ntiles, tile_rows, stream_win);           \
   }                                                                                            \
   struct NAME##_vgo {                                                                          \
     template <int RB, int U, bool NT>                                                          \
     static void go(const LaunchTable& t, hipStream_t s) {                                      \
+      const int sw = t.sched.nontemporal >= 2 ? 1 : 0; /* streaming window staging */          \
       if (t.partial_win)                                                                       \
         hipLaunchKernelGGL((NAME##_vec<RB, U, NT, false>), dim3(t.grid), dim3(t.sched.block_threads), \
                            (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                   \
-                           t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows);  \
+                           t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows, sw); \
       else                                                                                     \
         hipLaunchKernelGGL((NAME##_vec<RB, U, NT, true>), dim3(t.grid), dim3(t.sched.block_threads), \
                            (unsigned)t.win_bytes, s, t.jobs.as<GatherJob>(),                   \
-                           t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows);  \
+                           t.tile_start.as<int64_t>(), t.njobs, t.ntiles, t.sched.tile_rows, sw); \
     }                                                                                          \
   };                                                                                           \
   struct NAME##_go {                                                                           \

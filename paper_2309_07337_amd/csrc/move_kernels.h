@@ -293,7 +293,7 @@ __device__ __forceinline__ auto gas_ptr(T* p) {
 // windows miss some indices, than an LDS read plus a sparse global load.
 template <int RB, int U, bool NT, bool GAS>
 __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jobs, const int64_t* __restrict__ ts,
-                                                int njobs, int64_t ntiles, int tile_rows) {
+                                                int njobs, int64_t ntiles, int tile_rows, int stream_win) {
   constexpr int V = 16 / RB;
   using R = typename RawVec<RB>::type;
   using IV = typename IdxVec<RB>::type;
@@ -367,13 +367,20 @@ __device__ __forceinline__ void gather_vec_body(const GatherJob* __restrict__ jo
         const auto gp = gas_ptr<GAS>(reinterpret_cast<const u32x4*>(A16));
         u32x4* sp = reinterpret_cast<u32x4*>(s_dyn + (A16 - base));
         // all of a lane's staging loads in flight together (an 80 KiB window
-        // is at most 10 per lane with 512 lanes)
+        // is at most 10 per lane with 512 lanes); streaming loads when the
+        // schedule asks (a window is read once)
         constexpr int UW = 10;
         for (int i0 = tid; i0 < nv; i0 += bd * UW) {
           u32x4 w[UW];
+          if (stream_win) {
 #pragma unroll
-          for (int u = 0; u < UW; ++u)
-            if (i0 + u * bd < nv) w[u] = gp[i0 + u * bd];
+            for (int u = 0; u < UW; ++u)
+              if (i0 + u * bd < nv) w[u] = ldv<u32x4, true>(gp + i0 + u * bd);
+          } else {
+#pragma unroll
+            for (int u = 0; u < UW; ++u)
+              if (i0 + u * bd < nv) w[u] = gp[i0 + u * bd];
+          }
 #pragma unroll
           for (int u = 0; u < UW; ++u)
             if (i0 + u * bd < nv) sp[i0 + u * bd] = w[u];

@@ -193,7 +193,7 @@ Sched resolve_sched(const hx_sched* p, int kind, int row_bytes) {
   if (p->tile_rows > 0) s.tile_rows = p->tile_rows;
   if (p->block_threads > 0) s.block_threads = p->block_threads;
   if (p->blocks_per_cu > 0) s.blocks_per_cu = p->blocks_per_cu;
-  s.nontemporal = p->nontemporal ? 1 : 0;
+  s.nontemporal = p->nontemporal <= 0 ? 0 : (p->nontemporal >= 2 ? 2 : 1);
   s.per_neighbor = p->per_neighbor ? 1 : 0;
   if (p->unroll > 0) s.unroll = p->unroll <= 1 ? 1 : (p->unroll == 2 ? 2 : 4);
   if (p->push_pack == 1) s.push_pack = 1;
@@ -1215,6 +1215,14 @@ extern "C" int hx_batch_tune(hx_batch* b, void* stream) {
     if (!b->world && !(ph == PH_PACK && best.push_pack) && ph != PH_BWD) {
       Sched c = best;
       c.per_neighbor = 1;
+      consider(c);
+    }
+    // stage 6: streaming loads for the LDS window staging of 4- and 8-byte
+    // row gathers (a window is read once; it pays where the arena was not
+    // just left in the caches by the previous phase)
+    if (ph != PH_BWD && (rb == 4 || rb == 8) && best.pair_rows && best.lds_window && !(ph == PH_PACK && best.push_pack)) {
+      Sched c = best;
+      c.nontemporal = 2;
       consider(c);
     }
     if (rc == HX_SUCCESS) {

@@ -98,7 +98,7 @@ def test_world_without_halo_binds_empty_gradients(variant):
        ncols=st.sampled_from([1, 2, 3, 4, 16, 64]), f32=st.booleans(),
        tile=st.sampled_from([0, 1, 7, 64, 300, 4096]), bt=st.sampled_from([0, 256, 512, 1024]),
        bpc=st.sampled_from([0, 1, 2, 8, 1 << 20]), unroll=st.sampled_from([0, 1, 2, 4, 8]),
-       nt=st.booleans(), push=st.sampled_from([0, 1, 2]), win=st.sampled_from([0, 1, 2]),
+       nt=st.sampled_from([0, 1, 2]), push=st.sampled_from([0, 1, 2]), win=st.sampled_from([0, 1, 2]),
        pair=st.sampled_from([0, 1, 2]), per_nbr=st.booleans())
 def test_member_batches_under_random_schedules(members, ncols, f32, tile, bt, bpc, unroll, nt, push, win, pair,
                                                 per_nbr):
@@ -152,7 +152,7 @@ def test_member_batches_under_random_schedules(members, ncols, f32, tile, bt, bp
        seed=st.integers(0, 10_000), ppn=st.integers(1, 6), variant=st.sampled_from(["plain", "locality", "locality3"]),
        ncols=st.sampled_from([1, 2, 5]), f32=st.booleans(),
        tile=st.sampled_from([0, 3, 64, 1000]), bt=st.sampled_from([0, 256, 1024]),
-       bpc=st.sampled_from([0, 2, 1 << 20]), unroll=st.sampled_from([0, 1, 4]), nt=st.booleans(),
+       bpc=st.sampled_from([0, 2, 1 << 20]), unroll=st.sampled_from([0, 1, 4]), nt=st.sampled_from([0, 1, 2]),
        win=st.sampled_from([0, 1, 2]), pair=st.sampled_from([0, 1, 2]), direct=st.booleans())
 def test_worlds_under_random_schedules(n, R, mx, pf, seed, ppn, variant, ncols, f32, tile, bt, bpc, unroll, nt, win,
                                        pair, direct):
